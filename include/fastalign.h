@@ -1,0 +1,300 @@
+/*
+ * fastalign.h -- C ABI of the MI355X (gfx950) FastAlign hot path.
+ *
+ * The library computes the optimal-transport network alignment of Algorithm 1
+ * (§3.1) of the FastAlign paper: Phase 1 precomputes the S-independent costs,
+ * Phase 2 rebuilds the S-dependent costs from the sparse adjacencies and the
+ * dense plan, Phase 3 runs log-domain Sinkhorn (Eq. (3)) and recovers the plan
+ * (Eq. (4)).
+ *
+ * Conventions for every entry point:
+ *   - All array arguments are DEVICE pointers unless the comment says "host".
+ *     The caller allocates and frees every buffer; the library never allocates
+ *     device memory.  Workspaces are caller-provided byte buffers whose size is
+ *     returned by the matching *_workspace_size() query (256-byte alignment).
+ *   - Dense n1 x n2 matrices are row-major with leading dimension n2 and 64-bit
+ *     offsets.  Row index i runs over the nodes of G1, column index j over G2.
+ *   - `stream` is a hipStream_t (NULL selects the null stream).  Device entry
+ *     points enqueue work on it and return without waiting, except where a
+ *     comment says they synchronise.
+ *   - Every entry point returns an fa_status; nothing throws across the ABI.
+ *     On a non-OK status fa_last_error() returns a thread-local message.  Inputs
+ *     are validated before any work is enqueued; on FA_ERR_* no output has
+ *     been written unless stated otherwise.
+ *   - Dual vectors follow Eq. (3): a (length n2) pairs with the column marginal
+ *     nu = 1/n2, b (length n1) with the row marginal mu = 1/n1.  Duals are FP64.
+ */
+#ifndef FASTALIGN_H
+#define FASTALIGN_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  FA_OK = 0,
+  FA_WARN_NOT_CONVERGED = 1, /* finished, but the inner tolerance was not met */
+  FA_ERR_ARG = -1,           /* invalid scalar argument, null pointer, bad anchors */
+  FA_ERR_SHAPE = -2,         /* inconsistent sizes */
+  FA_ERR_CSR = -3,           /* malformed CSR (host-side checks) */
+  FA_ERR_WORKSPACE = -4,     /* workspace missing or smaller than required */
+  FA_ERR_NUMERIC = -6,       /* non-finite value where a finite one is required */
+  FA_ERR_HIP = -7,           /* a HIP runtime call failed */
+  FA_ERR_DEVICE = -8         /* the current device is not a gfx950 GPU */
+} fa_status;
+
+typedef enum { FA_F32 = 0, FA_BF16 = 1, FA_F64 = 2 } fa_dtype;
+
+/* Pattern-only CSR of an undirected graph (§2: adjacency A with 0/1 entries).
+ * rowptr: int64[n+1], colidx: int32[nnz], device.  Rows must be sorted and
+ * duplicate-free without self-loops, as fa_csr_build produces them. */
+typedef struct {
+  int32_t n;
+  int64_t nnz;
+  const int64_t *rowptr;
+  const int32_t *colidx;
+} fa_csr;
+
+/* Hyper-parameters of Algorithm 1 (the paper gives no values; see
+ * fa_default_params for this library's defaults). */
+typedef struct {
+  double eps;         /* Sinkhorn entropic regulariser epsilon (Eq. (1), Eq. (3)) */
+  double alpha;       /* positional vs attribute weight in C_node */
+  double beta;        /* restart weight of the positional encoding */
+  double lambda_e;    /* weight of C_edge (Eq. (2)) */
+  double lambda_n;    /* weight of C_nbr (Eq. (2)) */
+  double lambda_a;    /* weight of C_anc (Eq. (2)) */
+  double lambda_p;    /* weight of the proximal term -lambda_p * log S */
+  double eps_anchor;  /* epsilon inside C_anc = -log(eps_anchor + OneHot(L)) */
+  double delta_nbr;   /* C_nbr = -log(Abar1^T S Abar2 + delta_nbr) */
+  double tol;         /* inner stop: L1 column-marginal error <= tol (0: never) */
+  int32_t k_r;        /* positional-encoding iterations */
+  int32_t k_node;     /* node-cost propagation iterations */
+  int32_t outer_iters;/* outer (proximal) iterations */
+  int32_t inner_iters;/* cap on Sinkhorn iterations per outer iteration */
+  int32_t check_every;/* evaluate the stop rule every this many iterations (>=1) */
+  int32_t plan_dtype; /* FA_F32 or FA_BF16: storage of S and the SpMM intermediates */
+  int32_t feat_dtype; /* FA_F32 or FA_BF16: X-hat and R operands of fa_feature_sim */
+  int32_t feat_l2norm;/* 1: row-L2-normalise the attributes before the product */
+  int32_t warm_start; /* 0: cold duals; 1: learned row duals for the first solve */
+  int32_t chunk_rows; /* rows per Phase-2 chunk (0: automatic) */
+  int32_t profile;    /* 1: time every launch with HIP events (fa_stats.kernel_ms) */
+} fa_params;
+
+/* Run statistics returned by fa_align (host struct). */
+typedef struct {
+  int32_t outer_done;
+  int32_t inner_total;      /* Sinkhorn iterations summed over outer iterations */
+  int32_t fell_back;        /* 1 if the learned start missed tol and a cold solve replaced it */
+  int32_t converged_all;    /* 1 if every inner solve met tol */
+  double marg_err;          /* L1 column-marginal error of the last inner solve */
+  double phase_ms[4];       /* Phase 1, cost rebuild, Sinkhorn, plan (device time) */
+  int32_t inner_iters[64];  /* per outer iteration (first 64) */
+  double inner_err[64];
+  /* with params.profile: summed device time and launch count per kernel class:
+   * [0] column LSE partials, [1] column merge, [2] row LSE, [3] cost stage 1
+   * (left SpMM), [4] cost stage 2 (right SpMM + fused assembly), [5] plan */
+  double kernel_ms[6];
+  int32_t kernel_calls[6];
+} fa_stats;
+
+/* Thread-local message describing the last non-OK status. */
+const char *fa_last_error(void);
+
+/* Fill *p with this library's defaults: eps 0.05, alpha 0.5, beta 0.15,
+ * lambda_e = lambda_n = lambda_a = 1, lambda_p = eps_anchor = eps,
+ * delta_nbr 1e-30, tol 0, k_r 10, k_node 1, 10 outer x 50 inner iterations,
+ * check_every 1, FP32 plan and features, feat_l2norm 1, cold start. */
+void fa_default_params(fa_params *p);
+
+/* 0 if the current HIP device is a gfx950 GPU, else FA_ERR_DEVICE. */
+int fa_device_check(void);
+
+/* ----------------------------------------------------------------------- */
+/* Host-side graph input (§2; reading: undirected, symmetrised, self-loops   */
+/* dropped, duplicates merged, columns sorted).                              */
+/* ----------------------------------------------------------------------- */
+
+/* Build the CSR of an undirected graph from an edge list.
+ *   edges_uv   host int64[m*2], pairs (u, v) with 0 <= u, v < n
+ *   rowptr_out host int64[n+1]
+ *   colidx_out host int32[cap]
+ *   nnz_out    host: number of stored entries (also set when cap is too small)
+ * Returns FA_ERR_ARG for an endpoint out of range or n < 0, m < 0, and
+ * FA_ERR_SHAPE if cap < nnz (rowptr_out is then valid, colidx_out is not). */
+int fa_csr_build(int32_t n, int64_t m, const int64_t *edges_uv, int64_t *rowptr_out,
+                 int32_t *colidx_out, int64_t cap, int64_t *nnz_out);
+
+/* ----------------------------------------------------------------------- */
+/* Phase 1 building blocks (Algorithm 1, Phase 1)                            */
+/* ----------------------------------------------------------------------- */
+
+/* Row normalisation Abar = D^-1 A: inv_deg[i] = 1/deg_i, 0 for isolated nodes.
+ *   inv_deg float[A->n] (out). */
+int fa_row_normalize(const fa_csr *A, float *inv_deg, void *stream);
+
+/* Positional encoding: R^(0) one-hot at the anchor nodes (column l at node
+ * anchor_nodes[l]); then k steps of R <- (1-beta) Abar R + beta R^(0).
+ *   anchor_nodes int32[nL], distinct, in [0, A->n)
+ *   R, R_tmp     float[A->n * nL] row-major (out, scratch)
+ * Anchor validity is the caller's responsibility here (fa_align checks it). */
+int fa_positional(const fa_csr *A, const float *inv_deg, const int32_t *anchor_nodes,
+                  int32_t nL, double beta, int32_t k, float *R, float *R_tmp, void *stream);
+
+/* Sampled dense-dense product on the adjacency pattern (§3.3, SDDMM):
+ *   out[e] = <R[row(e),:], R[col(e),:]> * inv_deg[row(e)]   if scale_by_col == 0
+ *   out[e] = <R[row(e),:], R[col(e),:]> * inv_deg[col(e)]   if scale_by_col == 1
+ * i.e. the stored values of C1 = (R1 R1^T) o Abar1 (scale_by_col = 0) and of
+ * C2 = (R2 R2^T) o Abar2^T (scale_by_col = 1) in the CSR order of A.
+ *   R float[A->n * nL], out float[A->nnz]. */
+int fa_sddmm(const fa_csr *A, const float *inv_deg, const float *R, int32_t nL,
+             int32_t scale_by_col, float *out, void *stream);
+
+/* Row-wise L2 normalisation (zero rows stay zero), written as out_dtype.
+ *   X float[n*d]; out float or bf16 [n*d]. */
+int fa_l2_normalize(const float *X, int32_t n, int32_t d, void *out, int32_t out_dtype,
+                    void *stream);
+
+/* Node similarity (Algorithm 1, Phase 1):
+ *   C_node = alpha * exp(-R1 R2^T) + (1 - alpha) * exp(-X1 X2^T)
+ * as one fused matrix-core product with an exponential epilogue.
+ *   X1 [n1*d], X2 [n2*d]   (dtype x_dtype: FA_F32 or FA_BF16; d may be 0)
+ *   R1 [n1*nL], R2 [n2*nL] (dtype r_dtype; nL may be 0)
+ *   C_node float[n1*n2] (out).  FP32 operands use FP32 MFMA, BF16 operands
+ *   BF16 MFMA; accumulation is FP32 in both. */
+int fa_feature_sim(const void *X1, const void *X2, int32_t n1, int32_t n2, int32_t d,
+                   int32_t x_dtype, const void *R1, const void *R2, int32_t nL,
+                   int32_t r_dtype, double alpha, float *C_node, void *stream);
+
+/* Workspace for fa_propagate and fa_cost (the block-transposed SpMM
+ * intermediates of one row chunk).  chunk_rows 0 means all n1 rows. */
+size_t fa_cost_workspace_size(int32_t n1, int32_t n2, int32_t plan_dtype, int32_t chunk_rows);
+
+/* Node-cost propagation, k times C <- Abar1 C Abar2^T (two SpMMs per step).
+ *   C     float[n1*n2] in/out;  C_tmp float[n1*n2] scratch
+ *   ws    >= fa_cost_workspace_size(n1, n2, FA_F32, chunk_rows) bytes. */
+int fa_propagate(const fa_csr *A1, const float *inv_deg1, const fa_csr *A2,
+                 const float *inv_deg2, float *C, float *C_tmp, int32_t k, int32_t chunk_rows,
+                 void *ws, size_t ws_bytes, void *stream);
+
+/* Phase 2 cost rebuild (Algorithm 1, Phase 2; Eq. (2); §3.5 fusion):
+ *   C_new = C_node + lambda_e * C1 S C2^T - lambda_n * log(Abar1^T S Abar2 + delta)
+ *           + lambda_a * C_anc - lambda_p * log S,
+ *   log S_ij = (a_j + b_i - C_prev_ij) / eps   (the plan of the previous duals).
+ *   w1  float[A1->nnz]: C1 values in A1's CSR order (fa_sddmm, scale_by_col 0)
+ *   w2  float[A2->nnz]: C2 values in A2's CSR order (fa_sddmm, scale_by_col 1)
+ *   S   [n1*n2] of dtype s_dtype (FA_F32/FA_BF16): the current plan
+ *   partner int32[n1]: anchor partner in G2 of node i, or -1
+ *   a double[n2], b double[n1]: duals that produced S from C_prev
+ *   C_inout float[n1*n2]: C_prev in, C_new out (updated in place, row chunk by
+ *   row chunk).  ws >= fa_cost_workspace_size(n1, n2, s_dtype, p->chunk_rows). */
+int fa_cost(const fa_csr *A1, const fa_csr *A2, const float *w1, const float *w2,
+            const float *inv_deg1, const float *inv_deg2, const void *S, int32_t s_dtype,
+            const float *C_node, const int32_t *partner, const double *a, const double *b,
+            const fa_params *p, float *C_inout, void *ws, size_t ws_bytes, void *stream);
+
+/* ----------------------------------------------------------------------- */
+/* Phase 3 (Eq. (3), Eq. (4))                                                */
+/* ----------------------------------------------------------------------- */
+
+size_t fa_sinkhorn_workspace_size(int32_t n1, int32_t n2);
+
+/* Log-domain Sinkhorn on a fixed cost C (Eq. (3)): each iteration updates a
+ * (column log-sum-exp over i) and then b (row log-sum-exp over j).  The L1
+ * column-marginal error sum_j |sum_i S_ij - 1/n2| of the state after an
+ * iteration is evaluated (in FP64) by the next column pass; every
+ * check_every iterations the loop stops when tol > 0 and err <= tol.
+ *   a double[n2], b double[n1]: starting duals in, final duals out
+ *   dev_iters int32[1], dev_err double[1] (device, out): iterations done and the
+ *   final marginal error.  The loop never waits for the host.
+ * If host_iters/host_err are non-NULL the call synchronises the stream and
+ * copies the two results to them. */
+int fa_sinkhorn(const float *C, int32_t n1, int32_t n2, double eps, double *a, double *b,
+                int32_t max_iter, double tol, int32_t check_every, int32_t *dev_iters,
+                double *dev_err, int32_t *host_iters, double *host_err, void *ws,
+                size_t ws_bytes, void *stream);
+
+/* Plan recovery S_ij = exp((a_j + b_i - C_ij)/eps) (Eq. (4)) stored as s_dtype
+ * (FA_F32 or FA_BF16, round-to-nearest-even).  If argmax is non-NULL it also
+ * writes argmax_j (a_j + b_i - C_ij) per row i (lowest j on ties), int32[n1]. */
+int fa_plan(const float *C, int32_t n1, int32_t n2, double eps, const double *a,
+            const double *b, void *S, int32_t s_dtype, int32_t *argmax, void *stream);
+
+/* ----------------------------------------------------------------------- */
+/* End to end (Algorithm 1)                                                  */
+/* ----------------------------------------------------------------------- */
+
+size_t fa_align_workspace_size(int32_t n1, int32_t n2, int32_t d, int32_t nL,
+                               int64_t nnz1, int64_t nnz2, const fa_params *p);
+
+/* Align G1 and G2: Phase 1 once, then p->outer_iters times Phase 2 + Phase 3.
+ *   X1 float[n1*d], X2 float[n2*d] (d may be 0: no attributes)
+ *   anchors int32[nL*2]: pairs (node in G1, node in G2); each node may appear
+ *     in at most one pair (FA_ERR_ARG otherwise; checked on the device, this
+ *     check synchronises once)
+ *   mlp_weights float[fa_mlp_param_count()] or NULL; required if p->warm_start
+ *   S_out [n1*n2] of p->plan_dtype (out): the final plan
+ *   a_out double[n2], b_out double[n1], argmax_out int32[n1] (out)
+ *   stats host fa_stats (out), may be NULL
+ * The call synchronises the stream once at the end to fill stats.  Returns
+ * FA_WARN_NOT_CONVERGED if tol > 0 and some inner solve missed it. */
+int fa_align(const fa_csr *A1, const fa_csr *A2, const float *X1, const float *X2, int32_t d,
+             const int32_t *anchors, int32_t nL, const fa_params *p, const float *mlp_weights,
+             void *S_out, double *a_out, double *b_out, int32_t *argmax_out, fa_stats *stats,
+             void *ws, size_t ws_bytes, void *stream);
+
+/* ----------------------------------------------------------------------- */
+/* Learned warm start: per-node inputs and a 3-layer MLP                     */
+/* ----------------------------------------------------------------------- */
+
+/* Width of the per-node input vector produced by fa_node_features. */
+int32_t fa_node_feature_dim(void);
+
+/* Per-node inputs of the warm-start network for one graph of an aligned pair:
+ * log(1+deg), the 16-dim projection of the L2-normalised attributes by the
+ * fixed matrix `proj` (float[d*16], may be NULL when d == 0), hop distance to
+ * the nearest anchor (capped at 8, divided by 8), the random-walk anchor mass
+ * Abar^h 1_anchor for h = 1, 2, 3, an is-anchor flag, log(n)/16 and a bias 1.
+ *   A, inv_deg: this graph; anchor_nodes int32[nL] on this side
+ *   X float[n*d]; out float[n * fa_node_feature_dim()] (row-major)
+ *   ws >= fa_node_features_workspace_size(n) bytes. */
+size_t fa_node_features_workspace_size(int32_t n);
+int fa_node_features(const fa_csr *A, const float *inv_deg, const float *X, int32_t d,
+                     const float *proj, const int32_t *anchor_nodes, int32_t nL, float *out,
+                     void *ws, size_t ws_bytes, void *stream);
+
+/* Parameter layout of the MLP  in -> 256 -> 256 -> 1 with SiLU activations:
+ * W1[in*256], b1[256], W2[256*256], b2[256], W3[256], b3[1] (row-major, x @ W). */
+int32_t fa_mlp_param_count(void);
+
+/* Floats of the activation buffer the MLP entry points need for N rows. */
+size_t fa_mlp_act_floats(int32_t N);
+
+/* Forward pass: y[N] = scale * (h2 . W3 + b3) + offset with h1 = SiLU(x W1 + b1),
+ * h2 = SiLU(h1 W2 + b2).  act float[fa_mlp_act_floats(N)] receives the
+ * pre-activations and activations of both hidden layers for fa_mlp_backward. */
+int fa_mlp_forward(const float *params, const float *x, int32_t N, float *y, float *act,
+                   void *stream);
+
+/* Backward pass of the mean squared error L = mean((y - t)^2) given the act of
+ * the matching fa_mlp_forward call (act is consumed: overwritten with
+ * intermediate gradients): grad float[fa_mlp_param_count()] (out, overwritten;
+ * the scale and offset entries are not trained and get 0) and loss double[1]
+ * (device, out). */
+int fa_mlp_backward(const float *params, const float *x, const float *t, int32_t N,
+                    const float *act, float *grad, double *loss, void *stream);
+
+/* One Adam step (lr, beta1, beta2, eps_adam, step >= 1) on params with moment
+ * buffers m, v (float[count], zero-initialised by the caller). */
+int fa_adam_step(float *params, const float *grad, float *m, float *v, int32_t count,
+                 double lr, double beta1, double beta2, double eps_adam, int32_t step,
+                 void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FASTALIGN_H */

@@ -1,0 +1,474 @@
+// Phase 3 of Algorithm 1: log-domain Sinkhorn (Eq. (3)) and plan recovery (Eq. (4)).
+//
+// Each pass streams the FP32 cost once with fused shift / exp / sum (§3.5): the
+// exponent (a_j + b_i - C_ij)/eps is assembled in FP64 (duals are FP64), shifted
+// by the running maximum in FP64, and only the shifted value (at most 0, small
+// where it matters) is rounded to FP32 for exp2; sums accumulate in FP64.
+// Shifting by the current duals turns each update into an increment,
+//   a_j <- a_j + eps * (log nu_j - LSE_i((a_j + b_i - C_ij)/eps)),
+//   b_i <- b_i + eps * (log mu_i - LSE_j((a_j + b_i - C_ij)/eps)),
+// which is Eq. (3) rewritten, so FP32 only ever sees well-scaled exponents.
+//
+// The column pass (a-update) reads row-major tiles: workgroups own a column strip
+// and a row range and leave a (max, sum) partial per column; a merge kernel folds
+// the partials in a fixed order (deterministic, no float atomics).  The same
+// merge yields the column sums of the current plan, i.e. the L1 marginal error
+// of the previous iteration, for free.  The row pass (b-update) gives each
+// workgroup four rows and reduces across the workgroup with wavefront shuffles.
+//
+// The loop never waits for the host: a device control word marks convergence and
+// every later kernel of the loop returns at its first instruction.
+#include "fa_common.h"
+#include "fa_internal.h"
+
+namespace fa {
+
+struct SinkCtl {
+  int32_t done;
+  int32_t iters;
+  int32_t which;    // buffer (0: caller's a, 1: scratch) that holds the final a
+  uint32_t arrive;  // last-block counter of the merge kernel
+};
+
+struct SinkLayout {
+  int V, ncolblk, nsplit, rows_per_split, nmerge;
+};
+
+static SinkLayout sink_layout(int32_t n1, int32_t n2) {
+  SinkLayout L;
+  L.V = (n2 % 4 == 0) ? 4 : 1;
+  L.ncolblk = ceil_div(n2, 256 * L.V);
+  int want = ceil_div(2048, L.ncolblk > 0 ? L.ncolblk : 1);
+  int maxs = n1 / 16 > 1 ? n1 / 16 : 1;
+  L.nsplit = want < 1 ? 1 : (want > maxs ? maxs : want);
+  L.rows_per_split = ceil_div(n1 > 0 ? n1 : 1, L.nsplit);
+  L.nmerge = ceil_div(n2, 256);
+  return L;
+}
+
+size_t sinkhorn_ws_bytes(int32_t n1, int32_t n2) {
+  SinkLayout L = sink_layout(n1, n2);
+  Sizer z;
+  z.take<double>(static_cast<size_t>(L.nsplit) * n2);
+  z.take<double>(static_cast<size_t>(L.nsplit) * n2);
+  z.take<double>(n2);
+  z.take<double>(L.nmerge + 1);
+  z.take<SinkCtl>(1);
+  z.take<double>(1);
+  return z.off;
+}
+
+int carve_sinkhorn(Carver &cv, int32_t n1, int32_t n2, SinkWs &w) {
+  SinkLayout L = sink_layout(n1, n2);
+  w.pm = cv.take<double>(static_cast<size_t>(L.nsplit) * n2);
+  w.ps = cv.take<double>(static_cast<size_t>(L.nsplit) * n2);
+  w.a_next = cv.take<double>(n2);
+  w.errp = cv.take<double>(L.nmerge + 1);
+  w.ctl = reinterpret_cast<int32_t *>(cv.take<SinkCtl>(1));
+  w.err = cv.take<double>(1);
+  w.nsplit = L.nsplit;
+  w.nerrblk = L.nmerge;
+  return cv.ok ? FA_OK : FA_ERR_WORKSPACE;
+}
+
+template <int V>
+struct Vec;
+template <>
+struct Vec<1> {
+  static __device__ inline void load(const float *p, float *o) { o[0] = p[0]; }
+};
+template <>
+struct Vec<4> {
+  static __device__ inline void load(const float *p, float *o) {
+    float4 t = *reinterpret_cast<const float4 *>(p);
+    o[0] = t.x;
+    o[1] = t.y;
+    o[2] = t.z;
+    o[3] = t.w;
+  }
+};
+
+// Column pass, part 1: per (column strip, row range) partial LSE of
+// y_ij = (a_j + b_i - C_ij) * log2(e)/eps over the rows of the range.
+template <int V>
+__global__ __launch_bounds__(256) void k_lse_col_partial(const float *__restrict__ C, int32_t n1, int32_t n2,
+                                                         const double *__restrict__ bufA0,
+                                                         const double *__restrict__ bufA1, int32_t cur,
+                                                         const double *__restrict__ b, double k2,
+                                                         int32_t rows_per_split, double *__restrict__ pm,
+                                                         double *__restrict__ ps,
+                                                         const SinkCtl *__restrict__ ctl) {
+  if (ctl->done) return;
+  const double *a = cur ? bufA1 : bufA0;
+  const int j = (blockIdx.x * 256 + threadIdx.x) * V;
+  const int split = blockIdx.y;
+  const int r0 = split * rows_per_split;
+  const int r1 = min(n1, r0 + rows_per_split);
+  if (j >= n2) return;
+  double ak[V], m[V], s[V];
+#pragma unroll
+  for (int v = 0; v < V; ++v) {
+    ak[v] = a[j + v] * k2;
+    m[v] = -INFINITY;
+    s[v] = 0.0;
+  }
+  constexpr int U = 4;
+  for (int i = r0; i < r1; i += U) {
+    double x[U][V];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      if (i + u < r1) {
+        const double bk = b[i + u] * k2;
+        float c[V];
+        Vec<V>::load(C + static_cast<int64_t>(i + u) * n2 + j, c);
+#pragma unroll
+        for (int v = 0; v < V; ++v) x[u][v] = fma(-static_cast<double>(c[v]), k2, ak[v] + bk);
+      } else {
+#pragma unroll
+        for (int v = 0; v < V; ++v) x[u][v] = -INFINITY;
+      }
+    }
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+      double mx = x[0][v];
+#pragma unroll
+      for (int u = 1; u < U; ++u) mx = fmax(mx, x[u][v]);
+      if (mx > m[v]) {
+        s[v] *= static_cast<double>(exp2f(static_cast<float>(m[v] - mx)));
+        m[v] = mx;
+      }
+      float t = 0.f;
+#pragma unroll
+      for (int u = 0; u < U; ++u) t += exp2f(static_cast<float>(x[u][v] - m[v]));
+      s[v] += static_cast<double>(t);
+    }
+  }
+#pragma unroll
+  for (int v = 0; v < V; ++v) {
+    pm[static_cast<int64_t>(split) * n2 + j + v] = m[v];
+    ps[static_cast<int64_t>(split) * n2 + j + v] = s[v];
+  }
+}
+
+// Column pass, part 2: fold the partials of each column in split order, form the
+// new a_j (into the other buffer) and the column's marginal violation; the last
+// workgroup to finish sums the violations in block order and applies the stop rule.
+__global__ __launch_bounds__(256) void k_lse_col_merge(int32_t n2, int32_t nsplit, const double *__restrict__ pm,
+                                                       const double *__restrict__ ps, double *__restrict__ bufA0,
+                                                       double *__restrict__ bufA1, int32_t cur, double eps,
+                                                       double log_nu, double nu, double *__restrict__ errp,
+                                                       SinkCtl *__restrict__ ctl, int32_t it, int32_t is_check,
+                                                       int32_t is_final, double tol, int32_t *__restrict__ out_iters,
+                                                       double *__restrict__ out_err) {
+  if (ctl->done) return;
+  const double *a = cur ? bufA1 : bufA0;
+  double *an = cur ? bufA0 : bufA1;
+  const int j = blockIdx.x * 256 + threadIdx.x;
+  double e = 0.0;
+  if (j < n2) {
+    double M = -INFINITY, S = 0.0;
+    for (int q = 0; q < nsplit; ++q) lse2_merge(M, S, pm[static_cast<int64_t>(q) * n2 + j], ps[static_cast<int64_t>(q) * n2 + j]);
+    const double l2 = M + log2(S);  // log2 of the column sum
+    an[j] = a[j] + eps * (log_nu - l2 * kLn2);
+    e = fabs(exp2(l2) - nu);
+  }
+  // deterministic block sum
+  __shared__ double red[4];
+  e = wave_sum(e);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = e;
+  __syncthreads();
+  __shared__ bool last;
+  if (threadIdx.x == 0) {
+    errp[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
+    __threadfence();
+    const uint32_t prev = atomicAdd(&ctl->arrive, 1u);
+    last = (prev == gridDim.x - 1);
+  }
+  __syncthreads();
+  if (!last) return;
+  __threadfence();
+  double t = 0.0;
+  for (int q = threadIdx.x; q < static_cast<int>(gridDim.x); q += 256)
+    t += __hip_atomic_load(&errp[q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  t = wave_sum(t);
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = t;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const double err = (red[0] + red[1]) + (red[2] + red[3]);
+    ctl->arrive = 0u;
+    *out_err = err;
+    if (is_final || (is_check && tol > 0.0 && err <= tol)) {
+      ctl->done = 1;
+      ctl->iters = it;
+      ctl->which = cur;
+      *out_iters = it;
+    }
+  }
+}
+
+// Row pass (b-update): four rows per workgroup, the a-values of a column chunk are
+// loaded once and reused for the four rows.
+template <int V>
+__global__ __launch_bounds__(256) void k_lse_row(const float *__restrict__ C, int32_t n1, int32_t n2,
+                                                 const double *__restrict__ bufA0, const double *__restrict__ bufA1,
+                                                 int32_t nxt, double *__restrict__ b, double k2, double eps,
+                                                 double log_mu, const SinkCtl *__restrict__ ctl) {
+  if (ctl->done) return;
+  constexpr int R = 4;
+  const double *a = nxt ? bufA1 : bufA0;
+  const int i0 = blockIdx.x * R;
+  double bk[R], m[R], s[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    bk[r] = (i0 + r < n1) ? b[i0 + r] * k2 : 0.0;
+    m[r] = -INFINITY;
+    s[r] = 0.0;
+  }
+  for (int j = threadIdx.x * V; j < n2; j += 256 * V) {
+    double ak[V];
+#pragma unroll
+    for (int v = 0; v < V; ++v) ak[v] = a[j + v] * k2;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      if (i0 + r >= n1) continue;
+      float c[V];
+      Vec<V>::load(C + static_cast<int64_t>(i0 + r) * n2 + j, c);
+      double x[V];
+      double mx = -INFINITY;
+#pragma unroll
+      for (int v = 0; v < V; ++v) {
+        x[v] = fma(-static_cast<double>(c[v]), k2, ak[v] + bk[r]);
+        mx = fmax(mx, x[v]);
+      }
+      if (mx > m[r]) {
+        s[r] *= static_cast<double>(exp2f(static_cast<float>(m[r] - mx)));
+        m[r] = mx;
+      }
+      float t = 0.f;
+#pragma unroll
+      for (int v = 0; v < V; ++v) t += exp2f(static_cast<float>(x[v] - m[r]));
+      s[r] += static_cast<double>(t);
+    }
+  }
+  __shared__ double sm[R][4];
+  __shared__ double ss[R][4];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    double mr = m[r];
+    double sr = s[r];
+    wave_lse2(mr, sr);
+    if (lane == 0) {
+      sm[r][w] = mr;
+      ss[r][w] = sr;
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x < R) {
+    const int r = threadIdx.x;
+    if (i0 + r < n1) {
+      double M = sm[r][0];
+      double S = ss[r][0];
+      for (int q = 1; q < 4; ++q) lse2_merge(M, S, sm[r][q], ss[r][q]);
+      const double l2 = M + log2(S);
+      b[i0 + r] = b[i0 + r] + eps * (log_mu - l2 * kLn2);
+    }
+  }
+}
+
+// Final a: copy the scratch buffer into the caller's a if it holds the result.
+__global__ void k_final_a(double *__restrict__ a, const double *__restrict__ alt, int32_t n2,
+                          const SinkCtl *__restrict__ ctl) {
+  if (ctl->which != 1) return;
+  int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j < n2) a[j] = alt[j];
+}
+
+__global__ void k_sink_reset(SinkCtl *ctl) {
+  ctl->done = 0;
+  ctl->iters = 0;
+  ctl->which = 0;
+  ctl->arrive = 0u;
+}
+
+int run_sinkhorn(const float *C, int32_t n1, int32_t n2, double eps, double *a, double *b, int32_t max_iter,
+                 double tol, int32_t check_every, int32_t *dev_iters, double *dev_err, SinkWs &w,
+                 hipStream_t s, KTimer *tm) {
+  SinkLayout L = sink_layout(n1, n2);
+  SinkCtl *ctl = reinterpret_cast<SinkCtl *>(w.ctl);
+  const double k2 = kLog2e / eps;
+  const double log_nu = -log(static_cast<double>(n2)), nu = 1.0 / n2;
+  const double log_mu = -log(static_cast<double>(n1));
+  FA_LAUNCH(k_sink_reset, dim3(1), dim3(1), 0, s, ctl);
+  const dim3 gcol(L.ncolblk, L.nsplit), gmerge(L.nmerge), grow(ceil_div(n1, 4));
+  for (int it = 0; it <= max_iter; ++it) {
+    const int cur = it & 1;
+    const int is_final = it == max_iter;
+    const int is_check = it > 0 && (it % check_every == 0);
+    if (L.V == 4)
+      FA_TIMED(tm, KK_COL_PARTIAL, s,
+               FA_LAUNCH(k_lse_col_partial<4>, gcol, dim3(256), 0, s, C, n1, n2, a, w.a_next, cur, b, k2,
+                         L.rows_per_split, w.pm, w.ps, ctl));
+    else
+      FA_TIMED(tm, KK_COL_PARTIAL, s,
+               FA_LAUNCH(k_lse_col_partial<1>, gcol, dim3(256), 0, s, C, n1, n2, a, w.a_next, cur, b, k2,
+                         L.rows_per_split, w.pm, w.ps, ctl));
+    FA_TIMED(tm, KK_COL_MERGE, s,
+             FA_LAUNCH(k_lse_col_merge, gmerge, dim3(256), 0, s, n2, L.nsplit, w.pm, w.ps, a, w.a_next, cur, eps,
+                       log_nu, nu, w.errp, ctl, it, is_check, is_final, tol, dev_iters, dev_err));
+    if (is_final) break;
+    if (L.V == 4)
+      FA_TIMED(tm, KK_ROW, s,
+               FA_LAUNCH(k_lse_row<4>, grow, dim3(256), 0, s, C, n1, n2, a, w.a_next, 1 - cur, b, k2, eps, log_mu,
+                         ctl));
+    else
+      FA_TIMED(tm, KK_ROW, s,
+               FA_LAUNCH(k_lse_row<1>, grow, dim3(256), 0, s, C, n1, n2, a, w.a_next, 1 - cur, b, k2, eps, log_mu,
+                         ctl));
+  }
+  FA_LAUNCH(k_final_a, dim3(ceil_div(n2, 256)), dim3(256), 0, s, a, w.a_next, n2, ctl);
+  return FA_OK;
+}
+
+// 2^y for an FP64 exponent: integer part exact (ldexp), fraction through FP32 exp2.
+__device__ inline float exp2_split(double y) {
+  if (!(y > -1000.0)) return 0.0f;
+  if (y > 200.0) return INFINITY;
+  const double fl = floor(y);
+  return ldexpf(exp2f(static_cast<float>(y - fl)), static_cast<int>(fl));
+}
+
+// Plan S = exp2((a_j + b_i - C_ij) * log2(e)/eps), optional row argmax of the FP64 exponent.
+template <int V, typename TS>
+__global__ __launch_bounds__(256) void k_plan(const float *__restrict__ C, int32_t n1, int32_t n2,
+                                              const double *__restrict__ a, const double *__restrict__ b, double k2,
+                                              TS *__restrict__ S, int32_t *__restrict__ argmax) {
+  constexpr int R = 4;
+  const int i0 = blockIdx.x * R;
+  double bk[R], best[R];
+  int bidx[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    bk[r] = (i0 + r < n1) ? b[i0 + r] * k2 : 0.0;
+    best[r] = -INFINITY;
+    bidx[r] = 0x7fffffff;
+  }
+  for (int j = threadIdx.x * V; j < n2; j += 256 * V) {
+    double ak[V];
+#pragma unroll
+    for (int v = 0; v < V; ++v) ak[v] = a[j + v] * k2;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      if (i0 + r >= n1) continue;
+      const int64_t base = static_cast<int64_t>(i0 + r) * n2 + j;
+      float c[V];
+      Vec<V>::load(C + base, c);
+#pragma unroll
+      for (int v = 0; v < V; ++v) {
+        const double y = fma(-static_cast<double>(c[v]), k2, ak[v] + bk[r]);
+        store_from_f32<TS>(S, base + v, exp2_split(y));
+        if (y > best[r]) {
+          best[r] = y;
+          bidx[r] = j + v;
+        }
+      }
+    }
+  }
+  if (!argmax) return;
+  __shared__ double sb[R][4];
+  __shared__ int si[R][4];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    double v = best[r];
+    int id = bidx[r];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      const double v2 = __shfl_xor(v, o, 64);
+      const int id2 = __shfl_xor(id, o, 64);
+      if (v2 > v || (v2 == v && id2 < id)) {
+        v = v2;
+        id = id2;
+      }
+    }
+    if (lane == 0) {
+      sb[r][w] = v;
+      si[r][w] = id;
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x < R && i0 + static_cast<int>(threadIdx.x) < n1) {
+    const int r = threadIdx.x;
+    double v = sb[r][0];
+    int id = si[r][0];
+    for (int q = 1; q < 4; ++q)
+      if (sb[r][q] > v || (sb[r][q] == v && si[r][q] < id)) {
+        v = sb[r][q];
+        id = si[r][q];
+      }
+    argmax[i0 + r] = id;
+  }
+}
+
+int run_plan(const float *C, int32_t n1, int32_t n2, double eps, const double *a, const double *b, void *S,
+             int32_t sdt, int32_t *argmax, hipStream_t s, KTimer *tm) {
+  if (n1 == 0 || n2 == 0) return FA_OK;
+  const int tid = tm ? tm->begin(KK_PLAN, s) : -1;
+  const double k2 = kLog2e / eps;
+  const dim3 g(ceil_div(n1, 4));
+  const bool v4 = n2 % 4 == 0;
+  if (sdt == FA_BF16) {
+    if (v4)
+      FA_LAUNCH((k_plan<4, uint16_t>), g, dim3(256), 0, s, C, n1, n2, a, b, k2, static_cast<uint16_t *>(S), argmax);
+    else
+      FA_LAUNCH((k_plan<1, uint16_t>), g, dim3(256), 0, s, C, n1, n2, a, b, k2, static_cast<uint16_t *>(S), argmax);
+  } else {
+    if (v4)
+      FA_LAUNCH((k_plan<4, float>), g, dim3(256), 0, s, C, n1, n2, a, b, k2, static_cast<float *>(S), argmax);
+    else
+      FA_LAUNCH((k_plan<1, float>), g, dim3(256), 0, s, C, n1, n2, a, b, k2, static_cast<float *>(S), argmax);
+  }
+  if (tm) tm->end(tid, s);
+  return FA_OK;
+}
+
+}  // namespace fa
+
+using namespace fa;
+
+extern "C" size_t fa_sinkhorn_workspace_size(int32_t n1, int32_t n2) {
+  if (n1 <= 0 || n2 <= 0) return 256;
+  return sinkhorn_ws_bytes(n1, n2);
+}
+
+extern "C" int fa_sinkhorn(const float *C, int32_t n1, int32_t n2, double eps, double *a, double *b,
+                           int32_t max_iter, double tol, int32_t check_every, int32_t *dev_iters, double *dev_err,
+                           int32_t *host_iters, double *host_err, void *ws, size_t ws_bytes, void *stream) {
+  FA_REQUIRE(n1 > 0 && n2 > 0, FA_ERR_SHAPE, "fa_sinkhorn: n1 = %d, n2 = %d must be positive", n1, n2);
+  FA_REQUIRE(eps > 0 && max_iter >= 0 && check_every >= 1 && tol >= 0, FA_ERR_ARG,
+             "fa_sinkhorn: need eps > 0, max_iter >= 0, check_every >= 1, tol >= 0");
+  FA_REQUIRE(C && a && b && dev_iters && dev_err, FA_ERR_ARG, "fa_sinkhorn: null pointer");
+  FA_REQUIRE(ws && ws_bytes >= sinkhorn_ws_bytes(n1, n2), FA_ERR_WORKSPACE, "fa_sinkhorn: workspace %zu < %zu",
+             ws_bytes, sinkhorn_ws_bytes(n1, n2));
+  Carver cv(ws, ws_bytes);
+  SinkWs w;
+  FA_TRY(carve_sinkhorn(cv, n1, n2, w));
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  FA_TRY(run_sinkhorn(C, n1, n2, eps, a, b, max_iter, tol, check_every, dev_iters, dev_err, w, s));
+  if (host_iters || host_err) {
+    FA_HIP(hipStreamSynchronize(s));
+    if (host_iters) FA_HIP(hipMemcpy(host_iters, dev_iters, sizeof(int32_t), hipMemcpyDeviceToHost));
+    if (host_err) FA_HIP(hipMemcpy(host_err, dev_err, sizeof(double), hipMemcpyDeviceToHost));
+  }
+  return FA_OK;
+}
+
+extern "C" int fa_plan(const float *C, int32_t n1, int32_t n2, double eps, const double *a, const double *b, void *S,
+                       int32_t s_dtype, int32_t *argmax, void *stream) {
+  FA_REQUIRE(n1 >= 0 && n2 >= 0 && eps > 0, FA_ERR_ARG, "fa_plan: bad sizes or eps");
+  FA_REQUIRE(s_dtype == FA_F32 || s_dtype == FA_BF16, FA_ERR_ARG, "fa_plan: s_dtype %d", s_dtype);
+  if (n1 == 0 || n2 == 0) return FA_OK;
+  FA_REQUIRE(C && a && b && S, FA_ERR_ARG, "fa_plan: null pointer");
+  return run_plan(C, n1, n2, eps, a, b, S, s_dtype, argmax, static_cast<hipStream_t>(stream));
+}

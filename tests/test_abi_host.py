@@ -1,0 +1,78 @@
+"""CPU-side checks of the C-ABI library: it loads, exports every declared symbol,
+and its host-side CSR builder is bit-exact with the oracle's (no GPU needed)."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import fastalign_oracle as O
+from paper_2607_11952_amd.synth import CONFIGS, make_pair
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "fastalign.h")
+
+
+def declared_functions():
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(fa_[a-z0-9_]+)\s*\(", txt)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2607_11952_amd import binding
+    return binding.load()
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for must in ("fa_feature_sim", "fa_cost", "fa_sinkhorn", "fa_align"):
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol(lib):
+    from paper_2607_11952_amd import binding
+    names = declared_functions()
+    missing = [n for n in names if not hasattr(lib._dll, n)]
+    assert not missing, missing
+    assert set(names) == set(binding.EXPORTS)
+
+
+@pytest.mark.parametrize("cfg", ["c1", "c2"])
+def test_csr_build_bit_exact_with_oracle(lib, cfg):
+    from paper_2607_11952_amd import api
+    pr = make_pair(CONFIGS[cfg])
+    for n, e in ((pr.n1, pr.edges1), (pr.n2, pr.edges2)):
+        rp, ci = api.csr_build(n, e)
+        orp, oci = O.build_csr(n, e)
+        assert np.array_equal(rp, orp) and np.array_equal(ci, oci)
+        assert rp.dtype == np.int64 and ci.dtype == np.int32
+
+
+def test_csr_build_edge_cases(lib):
+    from paper_2607_11952_amd import api, binding
+    # empty graph, isolated nodes, loops and duplicates
+    rp, ci = api.csr_build(5, np.zeros((0, 2), np.int64))
+    assert list(rp) == [0] * 6 and ci.size == 0
+    e = np.array([[0, 0], [1, 2], [2, 1], [1, 2], [4, 1]])
+    rp, ci = api.csr_build(5, e)
+    orp, oci = O.build_csr(5, e)
+    assert np.array_equal(rp, orp) and np.array_equal(ci, oci)
+    with pytest.raises(binding.FastAlignError) as ex:
+        api.csr_build(3, np.array([[0, 3]]))
+    assert ex.value.status == binding.FA_ERR_ARG
+
+
+def test_default_params_and_sizes(lib):
+    from paper_2607_11952_amd import api, binding
+    p = api.params(eps=0.02)
+    assert p.lambda_p == 0.02 and p.eps_anchor == 0.02 and p.check_every == 1
+    assert lib.raw("fa_mlp_param_count")() == 24 * 256 + 256 + 256 * 256 + 256 + 256 + 3
+    # workspace queries are pure host functions
+    assert lib.raw("fa_sinkhorn_workspace_size")(1000, 1000) > 0
+    n = lib.raw("fa_align_workspace_size")(1000, 900, 32, 100, 8000, 7000, p)
+    assert n > 2 * 1000 * 900 * 4
+    p.plan_dtype = binding.FA_BF16
+    assert lib.raw("fa_cost_workspace_size")(1000, 900, binding.FA_BF16, 0) < \
+        lib.raw("fa_cost_workspace_size")(1000, 900, binding.FA_F32, 0)
