@@ -197,7 +197,7 @@ def n_chunk(n1, n2, zbytes):
 
 
 def cpu_baseline(cfg, n1_full, n2_full, T_full):
-    """Time the FP64 oracle on the same recipe at n = 1000 for 2 outer x inner-cap iterations,
+    """Time the FP64 oracle on the same recipe at n = 2500 for 2 outer x inner-cap iterations,
     then scale by (n1 n2) and the outer count to the full workload."""
     import dataclasses
 
@@ -205,7 +205,7 @@ def cpu_baseline(cfg, n1_full, n2_full, T_full):
 
     from oracle import fastalign_oracle as O
     from paper_2607_11952_amd.synth import make_pair
-    n_s, T_s = 1000, 2
+    n_s, T_s = 2500, 2
     pr = make_pair(cfg, n1=n_s)
     rp1, ci1 = O.build_csr(pr.n1, pr.edges1)
     rp2, ci2 = O.build_csr(pr.n2, pr.edges2)

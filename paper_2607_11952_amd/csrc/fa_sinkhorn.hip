@@ -38,7 +38,8 @@ static SinkLayout sink_layout(int32_t n1, int32_t n2) {
   SinkLayout L;
   L.V = (n2 % 4 == 0) ? 4 : 1;
   L.ncolblk = ceil_div(n2, 256 * L.V);
-  int want = ceil_div(2048, L.ncolblk > 0 ? L.ncolblk : 1);
+  // about eight rounds of resident workgroups, so the last round's tail is short
+  int want = ceil_div(16384, L.ncolblk > 0 ? L.ncolblk : 1);
   int maxs = n1 / 16 > 1 ? n1 / 16 : 1;
   L.nsplit = want < 1 ? 1 : (want > maxs ? maxs : want);
   L.rows_per_split = ceil_div(n1 > 0 ? n1 : 1, L.nsplit);
@@ -167,7 +168,12 @@ __global__ __launch_bounds__(256) void k_lse_col_merge(int32_t n2, int32_t nspli
   double e = 0.0;
   if (j < n2) {
     double M = -INFINITY, S = 0.0;
-    for (int q = 0; q < nsplit; ++q) lse2_merge(M, S, pm[static_cast<int64_t>(q) * n2 + j], ps[static_cast<int64_t>(q) * n2 + j]);
+    for (int q = 0; q < nsplit; ++q) M = fmax(M, pm[static_cast<int64_t>(q) * n2 + j]);
+    if (M > -INFINITY)
+      for (int q = 0; q < nsplit; ++q) {
+        const double mq = pm[static_cast<int64_t>(q) * n2 + j];
+        if (mq > -INFINITY) S += ps[static_cast<int64_t>(q) * n2 + j] * static_cast<double>(exp2f(static_cast<float>(mq - M)));
+      }
     const double l2 = M + log2(S);  // log2 of the column sum
     an[j] = a[j] + eps * (log_nu - l2 * kLn2);
     e = fabs(exp2(l2) - nu);
@@ -207,15 +213,15 @@ __global__ __launch_bounds__(256) void k_lse_col_merge(int32_t n2, int32_t nspli
   }
 }
 
-// Row pass (b-update): four rows per workgroup, the a-values of a column chunk are
-// loaded once and reused for the four rows.
+// Row pass (b-update): eight rows per workgroup, the a-values of a column chunk are
+// loaded once and reused for the eight rows.
 template <int V>
 __global__ __launch_bounds__(256) void k_lse_row(const float *__restrict__ C, int32_t n1, int32_t n2,
                                                  const double *__restrict__ bufA0, const double *__restrict__ bufA1,
                                                  int32_t nxt, double *__restrict__ b, double k2, double eps,
                                                  double log_mu, const SinkCtl *__restrict__ ctl) {
   if (ctl->done) return;
-  constexpr int R = 4;
+  constexpr int R = 8;
   const double *a = nxt ? bufA1 : bufA0;
   const int i0 = blockIdx.x * R;
   double bk[R], m[R], s[R];
@@ -301,7 +307,7 @@ int run_sinkhorn(const float *C, int32_t n1, int32_t n2, double eps, double *a, 
   const double log_nu = -log(static_cast<double>(n2)), nu = 1.0 / n2;
   const double log_mu = -log(static_cast<double>(n1));
   FA_LAUNCH(k_sink_reset, dim3(1), dim3(1), 0, s, ctl);
-  const dim3 gcol(L.ncolblk, L.nsplit), gmerge(L.nmerge), grow(ceil_div(n1, 4));
+  const dim3 gcol(L.ncolblk, L.nsplit), gmerge(L.nmerge), grow(ceil_div(n1, 8));
   for (int it = 0; it <= max_iter; ++it) {
     const int cur = it & 1;
     const int is_final = it == max_iter;

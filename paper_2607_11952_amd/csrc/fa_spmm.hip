@@ -46,13 +46,77 @@ __device__ inline void store16<uint16_t>(uint16_t *dst, const float *v) {
   }
 }
 
+// Vector loads of VW consecutive elements (aligned: the row length is a multiple
+// of VW whenever VW > 1) converted to FP32.
+template <typename T, int VW>
+struct VLoad;
+template <>
+struct VLoad<float, 1> {
+  static __device__ inline void run(const float *p, float *o) { o[0] = p[0]; }
+};
+template <>
+struct VLoad<float, 2> {
+  static __device__ inline void run(const float *p, float *o) {
+    const float2 t = *reinterpret_cast<const float2 *>(p);
+    o[0] = t.x;
+    o[1] = t.y;
+  }
+};
+template <>
+struct VLoad<uint16_t, 1> {
+  static __device__ inline void run(const uint16_t *p, float *o) { o[0] = bf16_to_f32(p[0]); }
+};
+template <>
+struct VLoad<uint16_t, 4> {
+  static __device__ inline void run(const uint16_t *p, float *o) {
+    const uint2 t = *reinterpret_cast<const uint2 *>(p);
+    o[0] = __uint_as_float(t.x << 16);
+    o[1] = __uint_as_float(t.x & 0xffff0000u);
+    o[2] = __uint_as_float(t.y << 16);
+    o[3] = __uint_as_float(t.y & 0xffff0000u);
+  }
+};
+
+__device__ inline int bcast_i(int v, int u) { return __builtin_amdgcn_readlane(v, u); }
+__device__ inline float bcast_f(float v, int u) { return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), u)); }
+
+template <typename T, int RW>
+__device__ inline void store_rows(T *dst, const float *v);
+template <>
+__device__ inline void store_rows<float, 8>(float *dst, const float *v) {
+  float4 *d = reinterpret_cast<float4 *>(dst);
+  d[0] = make_float4(v[0], v[1], v[2], v[3]);
+  d[1] = make_float4(v[4], v[5], v[6], v[7]);
+}
+template <>
+__device__ inline void store_rows<float, 4>(float *dst, const float *v) {
+  *reinterpret_cast<float4 *>(dst) = make_float4(v[0], v[1], v[2], v[3]);
+}
+template <>
+__device__ inline void store_rows<uint16_t, 4>(uint16_t *dst, const float *v) {
+  const uint32_t w0 = static_cast<uint32_t>(f32_to_bf16(v[0])) | (static_cast<uint32_t>(f32_to_bf16(v[1])) << 16);
+  const uint32_t w1 = static_cast<uint32_t>(f32_to_bf16(v[2])) | (static_cast<uint32_t>(f32_to_bf16(v[3])) << 16);
+  *reinterpret_cast<uint2 *>(dst) = make_uint2(w0, w1);
+}
+template <>
+__device__ inline void store_rows<uint16_t, 8>(uint16_t *dst, const float *v) {
+  uint32_t w[4];
+#pragma unroll
+  for (int t = 0; t < 4; ++t)
+    w[t] = static_cast<uint32_t>(f32_to_bf16(v[2 * t])) | (static_cast<uint32_t>(f32_to_bf16(v[2 * t + 1])) << 16);
+  *reinterpret_cast<uint4 *>(dst) = make_uint4(w[0], w[1], w[2], w[3]);
+}
+
 // Stage 1 (left SpMM into the block-transposed layout).
-//   grid.x = row block within the chunk, grid.y = 128-column tile; 4 waves, wave
-//   w owns rows 16w..16w+15 of the block, lane owns columns c0+lane, c0+64+lane.
+//   grid.x = row block within the chunk, grid.y = column tile of 64*VW columns;
+//   64/RW waves, wave w owns rows RW*w..RW*w+RW-1 of the block, lane owns VW consecutive
+//   columns and reads them with one vector load per gathered row segment.  A
+//   row's neighbour list is fetched 64 entries at a time with one coalesced load
+//   and broadcast lane by lane (readlane), so gathers never wait on index loads.
 //   Set a: Za[i,:] = rsa[i] * sum_e wa[e] S[col[e],:]          (wa/rsa may be null = 1)
 //   Set b: Zb[i,:] = sum_e csb[col[e]] S[col[e],:]            (only when TWO)
-template <typename TS, typename TZ, bool TWO>
-__global__ __launch_bounds__(256) void k_stage1(const int64_t *__restrict__ rowptr,
+template <typename TS, typename TZ, bool TWO, int VW, int RW>
+__global__ __launch_bounds__(64 * 64 / RW) void k_stage1(const int64_t *__restrict__ rowptr,
                                                 const int32_t *__restrict__ col,
                                                 const float *__restrict__ wa, const float *__restrict__ rsa,
                                                 const float *__restrict__ csb,
@@ -61,83 +125,93 @@ __global__ __launch_bounds__(256) void k_stage1(const int64_t *__restrict__ rowp
   const int lane = threadIdx.x & 63;
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int blk = blockIdx.x;
-  const int c0 = blockIdx.y * 128;
-  const int ca = c0 + lane, cb = c0 + 64 + lane;
-  const bool va = ca < n2, vb = cb < n2;
-  float za[16][2], zb[16][2];
+  const int c = blockIdx.y * (64 * VW) + lane * VW;
+  const bool valid = c < n2;
+  const TS *Sc = S + (valid ? c : 0);
+  float za[RW][VW], zb[RW][VW];
 #pragma unroll
-  for (int rr = 0; rr < 16; ++rr) {
-    const int rloc = blk * kZtRows + w * 16 + rr;
-    float a0 = 0.f, a1 = 0.f, b0 = 0.f, b1 = 0.f;
+  for (int rr = 0; rr < RW; ++rr) {
+    const int rloc = blk * kZtRows + w * RW + rr;
+    float a[VW], b[VW];
+#pragma unroll
+    for (int v = 0; v < VW; ++v) a[v] = b[v] = 0.f;
     if (rloc < nrows) {
       const int i = row0 + rloc;
       const int64_t e0 = rowptr[i], e1 = rowptr[i + 1];
-      int64_t e = e0;
-      for (; e + 4 <= e1; e += 4) {
-        float s0[4], s1[4], fa_[4], fb_[4];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          const TS *row = S + static_cast<int64_t>(col[e + u]) * n2;
-          s0[u] = va ? load_as_f32<TS>(row, ca) : 0.f;
-          s1[u] = vb ? load_as_f32<TS>(row, cb) : 0.f;
-          fa_[u] = wa ? wa[e + u] : 1.f;
-          if (TWO) fb_[u] = csb[col[e + u]];
+      for (int64_t base = e0; base < e1; base += 64) {
+        const int cnt = static_cast<int>(min<int64_t>(64, e1 - base));
+        int my_k = 0;
+        float my_a = 0.f, my_b = 0.f;
+        if (lane < cnt) {
+          my_k = col[base + lane];
+          my_a = wa ? wa[base + lane] : 1.f;
+          if (TWO) my_b = csb[my_k];
         }
+        int u = 0;
+        for (; u + 4 <= cnt; u += 4) {
+          float sv[4][VW];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          a0 += fa_[u] * s0[u];
-          a1 += fa_[u] * s1[u];
-          if (TWO) {
-            b0 += fb_[u] * s0[u];
-            b1 += fb_[u] * s1[u];
+          for (int q = 0; q < 4; ++q) {
+            const int k = bcast_i(my_k, u + q);
+            if (valid)
+              VLoad<TS, VW>::run(Sc + static_cast<int64_t>(k) * n2, sv[q]);
+            else
+#pragma unroll
+              for (int v = 0; v < VW; ++v) sv[q][v] = 0.f;
+          }
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const float fa = bcast_f(my_a, u + q);
+            const float fb = TWO ? bcast_f(my_b, u + q) : 0.f;
+#pragma unroll
+            for (int v = 0; v < VW; ++v) {
+              a[v] += fa * sv[q][v];
+              if (TWO) b[v] += fb * sv[q][v];
+            }
           }
         }
-      }
-      for (; e < e1; ++e) {
-        const TS *row = S + static_cast<int64_t>(col[e]) * n2;
-        const float s0 = va ? load_as_f32<TS>(row, ca) : 0.f;
-        const float s1 = vb ? load_as_f32<TS>(row, cb) : 0.f;
-        const float f = wa ? wa[e] : 1.f;
-        a0 += f * s0;
-        a1 += f * s1;
-        if (TWO) {
-          const float g = csb[col[e]];
-          b0 += g * s0;
-          b1 += g * s1;
+        for (; u < cnt; ++u) {
+          const int k = bcast_i(my_k, u);
+          float sv[VW];
+          if (valid)
+            VLoad<TS, VW>::run(Sc + static_cast<int64_t>(k) * n2, sv);
+          else
+#pragma unroll
+            for (int v = 0; v < VW; ++v) sv[v] = 0.f;
+          const float fa = bcast_f(my_a, u);
+          const float fb = TWO ? bcast_f(my_b, u) : 0.f;
+#pragma unroll
+          for (int v = 0; v < VW; ++v) {
+            a[v] += fa * sv[v];
+            if (TWO) b[v] += fb * sv[v];
+          }
         }
       }
       if (rsa) {
         const float r = rsa[i];
-        a0 *= r;
-        a1 *= r;
+#pragma unroll
+        for (int v = 0; v < VW; ++v) a[v] *= r;
       }
     }
-    za[rr][0] = a0;
-    za[rr][1] = a1;
-    zb[rr][0] = b0;
-    zb[rr][1] = b1;
-  }
-  // Each lane writes 16 consecutive rows of its two columns.
-  const int64_t base = static_cast<int64_t>(blk) * n2;
-  float v[16];
-  if (va) {
 #pragma unroll
-    for (int rr = 0; rr < 16; ++rr) v[rr] = za[rr][0];
-    store16<TZ>(Za + (base + ca) * kZtRows + w * 16, v);
-    if (TWO) {
-#pragma unroll
-      for (int rr = 0; rr < 16; ++rr) v[rr] = zb[rr][0];
-      store16<TZ>(Zb + (base + ca) * kZtRows + w * 16, v);
+    for (int v = 0; v < VW; ++v) {
+      za[rr][v] = a[v];
+      zb[rr][v] = b[v];
     }
   }
-  if (vb) {
+  if (!valid) return;
+  // Each lane writes RW consecutive rows of each of its VW columns.
+  const int64_t base = static_cast<int64_t>(blk) * n2;
+  float t[RW];
 #pragma unroll
-    for (int rr = 0; rr < 16; ++rr) v[rr] = za[rr][1];
-    store16<TZ>(Za + (base + cb) * kZtRows + w * 16, v);
+  for (int v = 0; v < VW; ++v) {
+#pragma unroll
+    for (int rr = 0; rr < RW; ++rr) t[rr] = za[rr][v];
+    store_rows<TZ, RW>(Za + (base + c + v) * kZtRows + w * RW, t);
     if (TWO) {
 #pragma unroll
-      for (int rr = 0; rr < 16; ++rr) v[rr] = zb[rr][1];
-      store16<TZ>(Zb + (base + cb) * kZtRows + w * 16, v);
+      for (int rr = 0; rr < RW; ++rr) t[rr] = zb[rr][v];
+      store_rows<TZ, RW>(Zb + (base + c + v) * kZtRows + w * RW, t);
     }
   }
 }
@@ -157,15 +231,15 @@ __device__ inline double log_accurate(float x) {
 }
 
 // Stage 2 (right SpMM from the block-transposed layout) with a fused epilogue.
-//   grid.x = 64-column output tile, grid.y = row block; wave w owns output
-//   columns j0+16w..j0+16w+15, lane = row of the block.
+//   grid.x = 64-column output tile, grid.y = row block; 8 waves, wave w owns
+//   output columns j0+8w..j0+8w+7, lane = row of the block.
 //   COST:  C[i,j] <- C_node + le*E - ln*log(P+delta) + la*C_anc + kp*(C_prev - a_j - b_i)
 //          with E = sum_e w2a[e] Za[:,col e], P = sum_e cs2b[col e] Zb[:,col e]
 //          (E, P accumulated in FP64; the tile of results is kept in FP64 until the
 //          epilogue rounds the assembled cost once)
 //   PLAIN: out[i,j] = rs[j] * sum_e Za[:,col e]
 template <typename TZ, bool COST>
-__global__ __launch_bounds__(256) void k_stage2(const int64_t *__restrict__ rowptr,
+__global__ __launch_bounds__(512) void k_stage2(const int64_t *__restrict__ rowptr,
                                                 const int32_t *__restrict__ col,
                                                 const float *__restrict__ w2a, const float *__restrict__ cs2b,
                                                 const float *__restrict__ rs, const TZ *__restrict__ Za,
@@ -181,54 +255,136 @@ __global__ __launch_bounds__(256) void k_stage2(const int64_t *__restrict__ rowp
   const int blk = blockIdx.y;
   const TZ *za = Za + static_cast<int64_t>(blk) * n2 * kZtRows + lane;
   const TZ *zb = COST ? Zb + static_cast<int64_t>(blk) * n2 * kZtRows + lane : nullptr;
-  for (int jj = 0; jj < 16; ++jj) {
-    const int j = j0 + w * 16 + jj;
-    double g = 0.0;
+  for (int jj = 0; jj < 8; ++jj) {
+    const int j = j0 + w * 8 + jj;
+    // per lane: FP32 -> one row (lane); BF16 -> two rows (2q, 2q+1) of every other
+    // neighbour (half-wave h), each lane loading 4 bytes
+    const int h = lane >> 5, q = lane & 31;
+    double E0 = 0.0, E1 = 0.0, P0 = 0.0, P1 = 0.0;
     if (j < n2) {
       const int64_t e0 = rowptr[j], e1 = rowptr[j + 1];
-      double E = 0.0, P = 0.0;
-      int64_t e = e0;
-      for (; e + 4 <= e1; e += 4) {
-        float x[4], y[4];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          const int64_t l = col[e + u];
-          x[u] = load_as_f32<TZ>(za, l * kZtRows);
-          if (COST) y[u] = cs2b[l] * load_as_f32<TZ>(zb, l * kZtRows);
-        }
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
+      for (int64_t base = e0; base < e1; base += 64) {
+        const int cnt = static_cast<int>(min<int64_t>(64, e1 - base));
+        int my_l = 0;
+        float my_w = 0.f, my_c = 0.f;
+        if (lane < cnt) {
+          my_l = col[base + lane];
           if (COST) {
-            E = fma(static_cast<double>(w2a[e + u]), static_cast<double>(x[u]), E);
-            P += static_cast<double>(y[u]);
-          } else {
-            E += static_cast<double>(x[u]);
+            my_w = w2a[base + lane];
+            my_c = cs2b[my_l];
+          }
+        }
+        if (sizeof(TZ) == 2) {
+          const uint32_t *ua = reinterpret_cast<const uint32_t *>(Za + static_cast<int64_t>(blk) * n2 * kZtRows) + q;
+          const uint32_t *ub =
+              COST ? reinterpret_cast<const uint32_t *>(Zb + static_cast<int64_t>(blk) * n2 * kZtRows) + q : nullptr;
+          for (int u = 0; u < cnt; u += 8) {
+            uint32_t xa[4], ya[4];
+            double wv[4], cv[4];
+            bool ok[4];
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+              const int ua_ = u + 2 * t, ub_ = u + 2 * t + 1;
+              const int uu = h ? ub_ : ua_;
+              const int l0 = bcast_i(my_l, ua_ < 64 ? ua_ : 63), l1 = bcast_i(my_l, ub_ < 64 ? ub_ : 63);
+              const int l = h ? l1 : l0;
+              ok[t] = uu < cnt;
+              xa[t] = ok[t] ? ua[static_cast<int64_t>(l) * (kZtRows / 2)] : 0u;
+              if (COST) {
+                ya[t] = ok[t] ? ub[static_cast<int64_t>(l) * (kZtRows / 2)] : 0u;
+                const float w0 = bcast_f(my_w, ua_ < 64 ? ua_ : 63), w1 = bcast_f(my_w, ub_ < 64 ? ub_ : 63);
+                const float c0 = bcast_f(my_c, ua_ < 64 ? ua_ : 63), c1 = bcast_f(my_c, ub_ < 64 ? ub_ : 63);
+                wv[t] = static_cast<double>(h ? w1 : w0);
+                cv[t] = static_cast<double>(h ? c1 : c0);
+              }
+            }
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+              if (!ok[t]) continue;
+              const double x0 = static_cast<double>(__uint_as_float(xa[t] << 16));
+              const double x1 = static_cast<double>(__uint_as_float(xa[t] & 0xffff0000u));
+              if (COST) {
+                E0 = fma(wv[t], x0, E0);
+                E1 = fma(wv[t], x1, E1);
+                P0 = fma(cv[t], static_cast<double>(__uint_as_float(ya[t] << 16)), P0);
+                P1 = fma(cv[t], static_cast<double>(__uint_as_float(ya[t] & 0xffff0000u)), P1);
+              } else {
+                E0 += x0;
+                E1 += x1;
+              }
+            }
+          }
+        } else {
+          int u = 0;
+          for (; u + 4 <= cnt; u += 4) {
+            float x[4], y[4];
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+              const int64_t l = bcast_i(my_l, u + t);
+              x[t] = load_as_f32<TZ>(za, l * kZtRows);
+              if (COST) y[t] = load_as_f32<TZ>(zb, l * kZtRows);
+            }
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+              if (COST) {
+                E0 = fma(static_cast<double>(bcast_f(my_w, u + t)), static_cast<double>(x[t]), E0);
+                P0 = fma(static_cast<double>(bcast_f(my_c, u + t)), static_cast<double>(y[t]), P0);
+              } else {
+                E0 += static_cast<double>(x[t]);
+              }
+            }
+          }
+          for (; u < cnt; ++u) {
+            const int64_t l = bcast_i(my_l, u);
+            const float x = load_as_f32<TZ>(za, l * kZtRows);
+            if (COST) {
+              E0 = fma(static_cast<double>(bcast_f(my_w, u)), static_cast<double>(x), E0);
+              P0 = fma(static_cast<double>(bcast_f(my_c, u)), static_cast<double>(load_as_f32<TZ>(zb, l * kZtRows)), P0);
+            } else {
+              E0 += static_cast<double>(x);
+            }
           }
         }
       }
-      for (; e < e1; ++e) {
-        const int64_t l = col[e];
-        const float x = load_as_f32<TZ>(za, l * kZtRows);
-        if (COST) {
-          E = fma(static_cast<double>(w2a[e]), static_cast<double>(x), E);
-          P += static_cast<double>(cs2b[l] * load_as_f32<TZ>(zb, l * kZtRows));
-        } else {
-          E += static_cast<double>(x);
-        }
-      }
-      if (COST)
-        g = cf.le * E - cf.ln * log_accurate(static_cast<float>(P + cf.delta));
-      else
-        g = static_cast<double>(rs[j]) * E;
     }
-    tile[lane][w * 16 + jj] = g;
+    if (sizeof(TZ) == 2) {
+      E0 += __shfl_xor(E0, 32, 64);
+      E1 += __shfl_xor(E1, 32, 64);
+      if (COST) {
+        P0 += __shfl_xor(P0, 32, 64);
+        P1 += __shfl_xor(P1, 32, 64);
+      }
+      if (h == 0) {
+        double g0 = 0.0, g1 = 0.0;
+        if (j < n2) {
+          if (COST) {
+            g0 = cf.le * E0 - cf.ln * log_accurate(static_cast<float>(P0 + cf.delta));
+            g1 = cf.le * E1 - cf.ln * log_accurate(static_cast<float>(P1 + cf.delta));
+          } else {
+            g0 = static_cast<double>(rs[j]) * E0;
+            g1 = static_cast<double>(rs[j]) * E1;
+          }
+        }
+        tile[2 * q][w * 8 + jj] = g0;
+        tile[2 * q + 1][w * 8 + jj] = g1;
+      }
+    } else {
+      double g = 0.0;
+      if (j < n2) {
+        if (COST)
+          g = cf.le * E0 - cf.ln * log_accurate(static_cast<float>(P0 + cf.delta));
+        else
+          g = static_cast<double>(rs[j]) * E0;
+      }
+      tile[lane][w * 8 + jj] = g;
+    }
   }
   __syncthreads();
   const int j = j0 + lane;
   if (j >= n2) return;
   const double aj = COST ? a[j] : 0.0;
-  for (int rr = 0; rr < 16; ++rr) {
-    const int r = w * 16 + rr;
+  for (int rr = 0; rr < 8; ++rr) {
+    const int r = w * 8 + rr;
     const int rloc = blk * kZtRows + r;
     if (rloc >= nrows) break;
     const int i = row0 + rloc;
@@ -263,11 +419,19 @@ static int cost_chunks(const CostArgs &c, int32_t chunk_rows, void *zt, hipStrea
   for (int32_t r0 = 0; r0 < n1; r0 += chunk_rows) {
     const int32_t nr = n1 - r0 < chunk_rows ? n1 - r0 : chunk_rows;
     const int nblk = ceil_div(nr, kZtRows);
-    FA_TIMED(tm, KK_STAGE1, s,
-             FA_LAUNCH((k_stage1<TS, TZ, true>), dim3(nblk, ceil_div(n2, 128)), dim3(256), 0, s, c.A1->rowptr,
-                       c.A1->colidx, c.w1, nullptr, c.inv1, static_cast<const TS *>(c.S), n2, r0, nr, Za, Zb));
+    constexpr int VW = sizeof(TS) == 2 ? 4 : 2;
+    constexpr int RW = sizeof(TS) == 2 ? 4 : 8;  // keeps the accumulators near 32 registers
+    if (n2 % VW == 0)
+      FA_TIMED(tm, KK_STAGE1, s,
+               FA_LAUNCH((k_stage1<TS, TZ, true, VW, RW>), dim3(nblk, ceil_div(n2, 64 * VW)), dim3(64 * 64 / RW), 0, s,
+                         c.A1->rowptr, c.A1->colidx, c.w1, nullptr, c.inv1, static_cast<const TS *>(c.S), n2, r0, nr,
+                         Za, Zb));
+    else
+      FA_TIMED(tm, KK_STAGE1, s,
+               FA_LAUNCH((k_stage1<TS, TZ, true, 1, 8>), dim3(nblk, ceil_div(n2, 64)), dim3(512), 0, s, c.A1->rowptr,
+                         c.A1->colidx, c.w1, nullptr, c.inv1, static_cast<const TS *>(c.S), n2, r0, nr, Za, Zb));
     FA_TIMED(tm, KK_STAGE2, s,
-             FA_LAUNCH((k_stage2<TZ, true>), dim3(ceil_div(n2, 64), nblk), dim3(256), 0, s, c.A2->rowptr,
+             FA_LAUNCH((k_stage2<TZ, true>), dim3(ceil_div(n2, 64), nblk), dim3(512), 0, s, c.A2->rowptr,
                        c.A2->colidx, c.w2, c.inv2, nullptr, Za, Zb, n2, r0, nr, c.C_node, c.partner, c.a, c.b, cf,
                        c.C));
   }
@@ -297,9 +461,13 @@ int run_propagate(const fa_csr *A1, const float *inv1, const fa_csr *A2, const f
     for (int32_t r0 = 0; r0 < n1; r0 += chunk_rows) {
       const int32_t nr = n1 - r0 < chunk_rows ? n1 - r0 : chunk_rows;
       const int nblk = ceil_div(nr, kZtRows);
-      FA_LAUNCH((k_stage1<float, float, false>), dim3(nblk, ceil_div(n2, 128)), dim3(256), 0, s, A1->rowptr,
-                A1->colidx, nullptr, inv1, nullptr, src, n2, r0, nr, Z, nullptr);
-      FA_LAUNCH((k_stage2<float, false>), dim3(ceil_div(n2, 64), nblk), dim3(256), 0, s, A2->rowptr,
+      if (n2 % 2 == 0)
+        FA_LAUNCH((k_stage1<float, float, false, 2, 8>), dim3(nblk, ceil_div(n2, 128)), dim3(512), 0, s, A1->rowptr,
+                  A1->colidx, nullptr, inv1, nullptr, src, n2, r0, nr, Z, nullptr);
+      else
+        FA_LAUNCH((k_stage1<float, float, false, 1, 8>), dim3(nblk, ceil_div(n2, 64)), dim3(512), 0, s, A1->rowptr,
+                  A1->colidx, nullptr, inv1, nullptr, src, n2, r0, nr, Z, nullptr);
+      FA_LAUNCH((k_stage2<float, false>), dim3(ceil_div(n2, 64), nblk), dim3(512), 0, s, A2->rowptr,
                 A2->colidx, nullptr, nullptr, inv2, Z, nullptr, n2, r0, nr, nullptr, nullptr, nullptr,
                 nullptr, cf, dst);
     }
