@@ -88,7 +88,7 @@ typedef struct {
 typedef struct {
   int32_t outer_done;
   int32_t inner_total;      /* Sinkhorn iterations summed over outer iterations */
-  int32_t fell_back;        /* 1 if the learned start missed tol and a cold solve replaced it */
+  int32_t fell_back;        /* 1 if the learned start was non-finite and the solve started cold */
   int32_t converged_all;    /* 1 if every inner solve met tol */
   double marg_err;          /* L1 column-marginal error of the last inner solve */
   double phase_ms[4];       /* Phase 1, cost rebuild, Sinkhorn, plan (device time) */

@@ -281,6 +281,8 @@ extern "C" int fa_align(const fa_csr *A1, const fa_csr *A2, const float *X1, con
 
   int32_t iters[64] = {0};
   double errs[64] = {0};
+  int32_t fell = 0;
+  if (p->warm_start && T > 0) FA_HIP(hipMemcpyAsync(&fell, B.bad + 2, sizeof(int32_t), hipMemcpyDeviceToHost, s));
   const int nrec = T < 64 ? T : 64;
   if (nrec > 0) {
     FA_HIP(hipMemcpyAsync(iters, B.st_iters, sizeof(int32_t) * nrec, hipMemcpyDeviceToHost, s));
@@ -301,7 +303,7 @@ extern "C" int fa_align(const fa_csr *A1, const fa_csr *A2, const float *X1, con
     memset(stats, 0, sizeof *stats);
     stats->outer_done = T;
     stats->inner_total = total;
-    stats->fell_back = 0;
+    stats->fell_back = fell != 0 ? 1 : 0;
     stats->converged_all = all_conv ? 1 : 0;
     stats->marg_err = nrec > 0 ? errs[nrec - 1] : 0.0;
     stats->phase_ms[0] = ms_p1;

@@ -1,0 +1,116 @@
+"""GPU parity of the learned warm start: per-node inputs, MLP forward/backward,
+Adam, and fa_align started from the network's row duals, against the FP64 oracle."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import fastalign_oracle as O
+from oracle import warm_oracle as W
+from paper_2607_11952_amd.synth import CONFIGS, PairConfig, make_pair
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def api(lib):
+    from paper_2607_11952_amd import api as A
+    return A
+
+
+def T32(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()
+
+
+def rand_params(seed, scale=1.0, offset=0.0):
+    r = np.random.default_rng(seed)
+    return W.pack(r.standard_normal((W.FEAT, W.HID)) / math.sqrt(W.FEAT), r.standard_normal(W.HID) * 0.1,
+                  r.standard_normal((W.HID, W.HID)) / math.sqrt(W.HID), r.standard_normal(W.HID) * 0.1,
+                  r.standard_normal(W.HID) / math.sqrt(W.HID), 0.2, scale, offset)
+
+
+@pytest.fixture(scope="module")
+def graph(api):
+    cfg = PairConfig("w", 700, "chung_lu", 8.0, noise=0.1, d=24, sigma=0.2, anchor_frac=0.05, seed=41)
+    pr = make_pair(cfg)
+    rp, ci = O.build_csr(pr.n1, pr.edges1)
+    A = api.DeviceCSR.from_host(pr.n1, rp, ci)
+    return pr, rp, ci, A
+
+
+def test_node_features(api, graph):
+    pr, rp, ci, A = graph
+    inv = api.row_normalize(A)
+    nodes = torch.from_numpy(pr.anchors[:, 0].copy()).cuda()
+    proj = W.gauss_projection(pr.X1.shape[1])
+    want = W.node_features(pr.n1, rp, ci, pr.X1, proj, pr.anchors[:, 0])
+    for p_dev in (T32(proj), None):   # explicit projection, and the library's own generator
+        got = api.node_features(A, inv, T32(pr.X1), nodes, p_dev).cpu().numpy().astype(np.float64)
+        assert np.array_equal(got[:, 18], want[:, 18])            # hop distance: exact
+        assert np.array_equal(got[:, 22], want[:, 22])            # anchor flag: exact
+        assert np.allclose(got, want, rtol=2e-5, atol=2e-6)
+
+
+@pytest.mark.parametrize("N", [1000, 37])
+def test_mlp_forward_backward_adam(api, N):
+    r = np.random.default_rng(N)
+    p = rand_params(N, scale=1.3, offset=-0.2)
+    x = r.standard_normal((N, W.FEAT))
+    t = r.standard_normal(N)
+    prm = T32(p)
+    y, act = api.mlp_forward(prm, T32(x))
+    p32 = prm.cpu().numpy().astype(np.float64)
+    y_ref, _ = W.mlp_forward(p32, x.astype(np.float32).astype(np.float64))
+    assert np.allclose(y.cpu().numpy(), y_ref, rtol=1e-4, atol=1e-5)
+    grad, loss = api.mlp_backward(prm, T32(x), T32(t), act)
+    loss_ref, g_ref = W.mlp_loss_grad(p32, x.astype(np.float32).astype(np.float64), t.astype(np.float32))
+    assert abs(loss.item() - loss_ref) <= 1e-5 * loss_ref
+    g = grad.cpu().numpy().astype(np.float64)
+    assert np.abs(g - g_ref).max() <= 1e-4 * np.abs(g_ref).max()
+    # Adam from zero moments, two steps
+    m = torch.zeros_like(prm)
+    v = torch.zeros_like(prm)
+    pr_, mr, vr = p32.copy(), np.zeros_like(p32), np.zeros_like(p32)
+    for step in (1, 2):
+        api.adam_step(prm, grad, m, v, step, lr=1e-3)
+        pr_, mr, vr = W.adam_step(pr_, g, mr, vr, step, lr=1e-3)
+    assert np.allclose(prm.cpu().numpy(), pr_, rtol=1e-6, atol=1e-6)
+
+
+def _warm_pair():
+    cfg = CONFIGS["c1"]
+    return make_pair(cfg, n1=500)
+
+
+def test_align_with_warm_start_matches_oracle(api):
+    pr = _warm_pair()
+    prm = rand_params(7, scale=3.0, offset=1.0)
+    rp1, ci1 = O.build_csr(pr.n1, pr.edges1)
+    rp2, ci2 = O.build_csr(pr.n2, pr.edges2)
+    F = W.node_features(pr.n1, rp1, ci1, pr.X1, W.gauss_projection(pr.X1.shape[1]), pr.anchors[:, 0])
+    pdev = T32(prm)
+    y_ref, _ = W.mlp_forward(pdev.cpu().numpy().astype(np.float64), F)
+    p = O.Params(eps=0.05, outer_iters=3, inner_iters=40)
+    ref = O.align(pr.n1, rp1, ci1, pr.n2, rp2, ci2, pr.X1, pr.X2, pr.anchors, p, b_init=0.05 * y_ref)
+    cold = O.align(pr.n1, rp1, ci1, pr.n2, rp2, ci2, pr.X1, pr.X2, pr.anchors, p)
+    inp = api.AlignInputs.from_pair(pr)
+    res = api.align(inp, api.params(eps=0.05, outer_iters=3, inner_iters=40, warm_start=1), mlp=pdev)
+    S = res.S.cpu().numpy().astype(np.float64)
+    assert np.abs(S - ref["S"]).max() / ref["S"].max() <= 1e-4
+    assert np.array_equal(res.argmax.cpu().numpy(), ref["argmax"])
+    # the start changes the first solve's iterates (a warm start that changes nothing would pass above trivially)
+    assert abs(ref["errs"][0] - cold["errs"][0]) > 1e-3 * cold["errs"][0]
+    assert abs(res.stats.inner_err[0] - ref["errs"][0]) <= 1e-3 * ref["errs"][0] + 1e-8
+
+
+def test_align_warm_start_non_finite_weights_fall_back_to_cold(api):
+    pr = _warm_pair()
+    inp = api.AlignInputs.from_pair(pr)
+    bad = T32(rand_params(8))
+    bad[5] = float("nan")
+    cold = api.align(inp, api.params(eps=0.05, outer_iters=2, inner_iters=20))
+    S_cold = cold.S.clone()
+    warm = api.align(inp, api.params(eps=0.05, outer_iters=2, inner_iters=20, warm_start=1), mlp=bad)
+    assert torch.equal(warm.S, S_cold)
+    assert warm.stats.fell_back == 1
