@@ -84,18 +84,22 @@ def _warm_pair():
 
 
 def test_align_with_warm_start_matches_oracle(api):
-    pr = _warm_pair()
+    """The small workload (ER n = 1000, 10 x 50), first solve started from the network.
+    (Shorter runs are worse conditioned: with 3 x 40 iterations on 500 nodes FP32
+    storage of C alone moves the oracle's plan by 5e-5.)"""
+    pr = make_pair(CONFIGS["c1"])
     prm = rand_params(7, scale=3.0, offset=1.0)
     rp1, ci1 = O.build_csr(pr.n1, pr.edges1)
     rp2, ci2 = O.build_csr(pr.n2, pr.edges2)
     F = W.node_features(pr.n1, rp1, ci1, pr.X1, W.gauss_projection(pr.X1.shape[1]), pr.anchors[:, 0])
     pdev = T32(prm)
     y_ref, _ = W.mlp_forward(pdev.cpu().numpy().astype(np.float64), F)
-    p = O.Params(eps=0.05, outer_iters=3, inner_iters=40)
+    p = O.Params(eps=0.05, outer_iters=10, inner_iters=50)
     ref = O.align(pr.n1, rp1, ci1, pr.n2, rp2, ci2, pr.X1, pr.X2, pr.anchors, p, b_init=0.05 * y_ref)
-    cold = O.align(pr.n1, rp1, ci1, pr.n2, rp2, ci2, pr.X1, pr.X2, pr.anchors, p)
+    p1 = O.Params(eps=0.05, outer_iters=1, inner_iters=50)
+    cold = O.align(pr.n1, rp1, ci1, pr.n2, rp2, ci2, pr.X1, pr.X2, pr.anchors, p1)
     inp = api.AlignInputs.from_pair(pr)
-    res = api.align(inp, api.params(eps=0.05, outer_iters=3, inner_iters=40, warm_start=1), mlp=pdev)
+    res = api.align(inp, api.params(eps=0.05, outer_iters=10, inner_iters=50, warm_start=1), mlp=pdev)
     S = res.S.cpu().numpy().astype(np.float64)
     assert np.abs(S - ref["S"]).max() / ref["S"].max() <= 1e-4
     assert np.array_equal(res.argmax.cpu().numpy(), ref["argmax"])
