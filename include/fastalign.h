@@ -76,7 +76,7 @@ typedef struct {
   int32_t outer_iters;/* outer (proximal) iterations */
   int32_t inner_iters;/* cap on Sinkhorn iterations per outer iteration */
   int32_t check_every;/* evaluate the stop rule every this many iterations (>=1) */
-  int32_t plan_dtype; /* FA_F32 or FA_BF16: storage of S and the SpMM intermediates */
+  int32_t plan_dtype; /* FA_F32 or FA_BF16: storage of S (SpMM intermediates stay FP32) */
   int32_t feat_dtype; /* FA_F32 or FA_BF16: X-hat and R operands of fa_feature_sim */
   int32_t feat_l2norm;/* 1: row-L2-normalise the attributes before the product */
   int32_t warm_start; /* 0: cold duals; 1: learned row duals for the first solve */
@@ -169,8 +169,10 @@ int fa_feature_sim(const void *X1, const void *X2, int32_t n1, int32_t n2, int32
                    int32_t x_dtype, const void *R1, const void *R2, int32_t nL,
                    int32_t r_dtype, double alpha, float *C_node, void *stream);
 
-/* Workspace for fa_propagate and fa_cost (the block-transposed SpMM
- * intermediates of one row chunk).  chunk_rows 0 means all n1 rows. */
+/* Workspace for fa_propagate and fa_cost (the block-transposed FP32 SpMM
+ * intermediates of one row chunk, 2 * ceil(chunk/64)*64 * n2 * 4 bytes).
+ * chunk_rows 0 means all n1 rows.  plan_dtype is accepted for symmetry with
+ * fa_params and does not change the size. */
 size_t fa_cost_workspace_size(int32_t n1, int32_t n2, int32_t plan_dtype, int32_t chunk_rows);
 
 /* Node-cost propagation, k times C <- Abar1 C Abar2^T (two SpMMs per step).

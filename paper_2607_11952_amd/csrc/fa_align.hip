@@ -14,16 +14,14 @@ namespace fa {
 
 struct AlignLayout {
   int32_t chunk_rows;
-  int32_t zdt;
 };
 
 static AlignLayout align_layout(int32_t n1, int32_t n2, const fa_params *p) {
   AlignLayout L;
-  L.zdt = p->plan_dtype == FA_BF16 ? FA_BF16 : FA_F32;
   int32_t cr = p->chunk_rows;
   if (cr <= 0) {
     // Keep the SpMM intermediate (two sets of chunk_rows x n2) near 16 GiB.
-    const double row_bytes = 2.0 * n2 * (L.zdt == FA_BF16 ? 2 : 4);
+    const double row_bytes = 2.0 * n2 * sizeof(float);
     const double cap = 16.0 * (1ull << 30);
     cr = static_cast<int32_t>(fmin(static_cast<double>(n1), floor(cap / fmax(row_bytes, 1.0))));
     cr = cr / kZtRows * kZtRows;
@@ -91,7 +89,7 @@ static void carve_align(Cv &cv, int32_t n1, int32_t n2, int32_t d, int32_t nL, i
   b.w2 = T((float *)0, nnz2 + 1);
   b.C_node = T((float *)0, N);
   b.C = T((float *)0, N);
-  b.zt = T((char *)0, zt_bytes(L.chunk_rows, n2, L.zdt));
+  b.zt = T((char *)0, zt_bytes(L.chunk_rows, n2));
   b.sink.pm = nullptr;
   b.st_iters = T((int32_t *)0, 64);
   b.st_err = T((double *)0, 64);
@@ -245,7 +243,7 @@ extern "C" int fa_align(const fa_csr *A1, const fa_csr *A2, const float *X1, con
   double t_cost = 0, t_sink = 0, t_plan = 0;
   for (int t = 0; t < T; ++t) {
     FA_HIP(hipEventRecord(ev[0], s));
-    FA_TRY(run_cost(c, L.chunk_rows, L.zdt, B.zt, s, tm));
+    FA_TRY(run_cost(c, L.chunk_rows, B.zt, s, tm));
     FA_HIP(hipEventRecord(ev[1], s));
     if (p->warm_start && t == 0) {
       FA_TRY(warm_start_duals(mlp_weights, B.feat, n1, B.act, p->eps, B.bad + 2, b_out, s));

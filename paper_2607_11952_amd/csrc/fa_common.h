@@ -115,6 +115,18 @@ __device__ inline void store_from_f32<float>(float *p, int64_t i, float v) { p[i
 template <>
 __device__ inline void store_from_f32<uint16_t>(uint16_t *p, int64_t i, float v) { p[i] = f32_to_bf16(v); }
 
+// Streaming (non-temporal) accesses for dense n1 x n2 operands that are touched
+// once per pass: at production sizes they cannot stay in L2 or MALL, so their
+// lines are marked to be evicted first and leave the caches to the dual vectors,
+// neighbour lists and gathered rows that are reused.
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+__device__ inline float ld_stream(const float *p) { return __builtin_nontemporal_load(p); }
+__device__ inline f32x4 ld_stream4(const float *p) {
+  return __builtin_nontemporal_load(reinterpret_cast<const f32x4 *>(p));
+}
+__device__ inline void st_stream(float *p, float v) { __builtin_nontemporal_store(v, p); }
+__device__ inline void st_stream(uint16_t *p, float v) { __builtin_nontemporal_store(f32_to_bf16(v), p); }
+
 // ---------------------------------------------------------------- reductions
 
 __device__ inline float wave_max(float v) {

@@ -28,7 +28,7 @@ int launch_feature_sim(const void *X1, const void *X2, int32_t n1, int32_t n2, i
 
 // Rows per block of the block-transposed SpMM intermediate.
 constexpr int kZtRows = 64;
-size_t zt_bytes(int32_t chunk_rows, int32_t n2, int32_t zdt);
+size_t zt_bytes(int32_t chunk_rows, int32_t n2);
 
 // Phase 2 cost rebuild over one row chunk at a time (Zt scratch of chunk_rows rows).
 struct CostArgs {
@@ -42,7 +42,7 @@ struct CostArgs {
   double lambda_e, lambda_n, lambda_a, lambda_p, eps, eps_anchor, delta;
   float *C;
 };
-int run_cost(const CostArgs &c, int32_t chunk_rows, int32_t zdt, void *zt, hipStream_t s, KTimer *tm = nullptr);
+int run_cost(const CostArgs &c, int32_t chunk_rows, void *zt, hipStream_t s, KTimer *tm = nullptr);
 int run_propagate(const fa_csr *A1, const float *inv1, const fa_csr *A2, const float *inv2, float *C,
                   float *C_tmp, int32_t k, int32_t chunk_rows, void *zt, hipStream_t s);
 

@@ -76,16 +76,40 @@ template <int V>
 struct Vec;
 template <>
 struct Vec<1> {
-  static __device__ inline void load(const float *p, float *o) { o[0] = p[0]; }
+  static __device__ inline void load(const float *p, float *o) { o[0] = ld_stream(p); }
 };
 template <>
 struct Vec<4> {
   static __device__ inline void load(const float *p, float *o) {
-    float4 t = *reinterpret_cast<const float4 *>(p);
+    const f32x4 t = ld_stream4(p);
     o[0] = t.x;
     o[1] = t.y;
     o[2] = t.z;
     o[3] = t.w;
+  }
+};
+
+// Vector store of V consecutive plan entries (one 16-byte FP32 or 8-byte BF16
+// store per lane for V = 4).
+template <typename T, int V>
+struct VStore {
+  static __device__ inline void run(T *p, const float *v) {
+#pragma unroll
+    for (int q = 0; q < V; ++q) store_from_f32<T>(p, q, v[q]);
+  }
+};
+template <>
+struct VStore<float, 4> {
+  static __device__ inline void run(float *p, const float *v) {
+    *reinterpret_cast<float4 *>(p) = make_float4(v[0], v[1], v[2], v[3]);
+  }
+};
+template <>
+struct VStore<uint16_t, 4> {
+  static __device__ inline void run(uint16_t *p, const float *v) {
+    const uint32_t w0 = static_cast<uint32_t>(f32_to_bf16(v[0])) | (static_cast<uint32_t>(f32_to_bf16(v[1])) << 16);
+    const uint32_t w1 = static_cast<uint32_t>(f32_to_bf16(v[2])) | (static_cast<uint32_t>(f32_to_bf16(v[3])) << 16);
+    *reinterpret_cast<uint2 *>(p) = make_uint2(w0, w1);
   }
 };
 
@@ -368,17 +392,18 @@ __global__ __launch_bounds__(256) void k_plan(const float *__restrict__ C, int32
     for (int r = 0; r < R; ++r) {
       if (i0 + r >= n1) continue;
       const int64_t base = static_cast<int64_t>(i0 + r) * n2 + j;
-      float c[V];
+      float c[V], sv[V];
       Vec<V>::load(C + base, c);
 #pragma unroll
       for (int v = 0; v < V; ++v) {
         const double y = fma(-static_cast<double>(c[v]), k2, ak[v] + bk[r]);
-        store_from_f32<TS>(S, base + v, exp2_split(y));
+        sv[v] = exp2_split(y);
         if (y > best[r]) {
           best[r] = y;
           bidx[r] = j + v;
         }
       }
+      VStore<TS, V>::run(S + base, sv);
     }
   }
   if (!argmax) return;

@@ -10,7 +10,9 @@
 // Both stages read contiguous multi-hundred-byte segments: stage 1 writes Z in a
 // block-transposed layout Zt[block][l][r] (64 rows r of a row block stored
 // contiguously per column l), so stage 2's gather of column l of a row block is
-// one 256-byte (FP32) or 128-byte (BF16) segment.  Neighbour lists are uniform
+// one 256-byte segment.  The intermediate is FP32 in both precision forms: the
+// BF16 form halves the reads of S, and an FP32 intermediate costs no time (stage 1
+// is gather-bound, stage 2 accumulates in FP64) while keeping E and P accurate.  Neighbour lists are uniform
 // per wavefront (one output row or column per wave), so indices and weights come
 // through the scalar cache and no lane diverges on the power-law degrees.
 #include "fa_common.h"
@@ -18,32 +20,9 @@
 
 namespace fa {
 
-size_t zt_bytes(int32_t chunk_rows, int32_t n2, int32_t zdt) {
+size_t zt_bytes(int32_t chunk_rows, int32_t n2) {
   const size_t nblk = (static_cast<size_t>(chunk_rows) + kZtRows - 1) / kZtRows;
-  const size_t el = zdt == FA_BF16 ? 2 : 4;
-  return 2 * align_up(nblk * kZtRows * static_cast<size_t>(n2) * el, 256);
-}
-
-template <typename T>
-__device__ inline void store16(T *dst, const float *v);
-template <>
-__device__ inline void store16<float>(float *dst, const float *v) {
-  float4 *d = reinterpret_cast<float4 *>(dst);
-#pragma unroll
-  for (int q = 0; q < 4; ++q) d[q] = make_float4(v[4 * q], v[4 * q + 1], v[4 * q + 2], v[4 * q + 3]);
-}
-template <>
-__device__ inline void store16<uint16_t>(uint16_t *dst, const float *v) {
-  uint4 *d = reinterpret_cast<uint4 *>(dst);
-#pragma unroll
-  for (int q = 0; q < 2; ++q) {
-    uint32_t w[4];
-#pragma unroll
-    for (int t = 0; t < 4; ++t)
-      w[t] = static_cast<uint32_t>(f32_to_bf16(v[8 * q + 2 * t])) |
-             (static_cast<uint32_t>(f32_to_bf16(v[8 * q + 2 * t + 1])) << 16);
-    d[q] = make_uint4(w[0], w[1], w[2], w[3]);
-  }
+  return 2 * align_up(nblk * kZtRows * static_cast<size_t>(n2) * sizeof(float), 256);
 }
 
 // Vector loads of VW consecutive elements (aligned: the row length is a multiple
@@ -67,45 +46,19 @@ struct VLoad<uint16_t, 1> {
   static __device__ inline void run(const uint16_t *p, float *o) { o[0] = bf16_to_f32(p[0]); }
 };
 template <>
-struct VLoad<uint16_t, 4> {
+struct VLoad<uint16_t, 2> {
   static __device__ inline void run(const uint16_t *p, float *o) {
-    const uint2 t = *reinterpret_cast<const uint2 *>(p);
-    o[0] = __uint_as_float(t.x << 16);
-    o[1] = __uint_as_float(t.x & 0xffff0000u);
-    o[2] = __uint_as_float(t.y << 16);
-    o[3] = __uint_as_float(t.y & 0xffff0000u);
+    const uint32_t t = *reinterpret_cast<const uint32_t *>(p);
+    o[0] = __uint_as_float(t << 16);
+    o[1] = __uint_as_float(t & 0xffff0000u);
   }
 };
 
 __device__ inline int bcast_i(int v, int u) { return __builtin_amdgcn_readlane(v, u); }
 __device__ inline float bcast_f(float v, int u) { return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), u)); }
 
-template <typename T, int RW>
-__device__ inline void store_rows(T *dst, const float *v);
-template <>
-__device__ inline void store_rows<float, 8>(float *dst, const float *v) {
-  float4 *d = reinterpret_cast<float4 *>(dst);
-  d[0] = make_float4(v[0], v[1], v[2], v[3]);
-  d[1] = make_float4(v[4], v[5], v[6], v[7]);
-}
-template <>
-__device__ inline void store_rows<float, 4>(float *dst, const float *v) {
-  *reinterpret_cast<float4 *>(dst) = make_float4(v[0], v[1], v[2], v[3]);
-}
-template <>
-__device__ inline void store_rows<uint16_t, 4>(uint16_t *dst, const float *v) {
-  const uint32_t w0 = static_cast<uint32_t>(f32_to_bf16(v[0])) | (static_cast<uint32_t>(f32_to_bf16(v[1])) << 16);
-  const uint32_t w1 = static_cast<uint32_t>(f32_to_bf16(v[2])) | (static_cast<uint32_t>(f32_to_bf16(v[3])) << 16);
-  *reinterpret_cast<uint2 *>(dst) = make_uint2(w0, w1);
-}
-template <>
-__device__ inline void store_rows<uint16_t, 8>(uint16_t *dst, const float *v) {
-  uint32_t w[4];
-#pragma unroll
-  for (int t = 0; t < 4; ++t)
-    w[t] = static_cast<uint32_t>(f32_to_bf16(v[2 * t])) | (static_cast<uint32_t>(f32_to_bf16(v[2 * t + 1])) << 16);
-  *reinterpret_cast<uint4 *>(dst) = make_uint4(w[0], w[1], w[2], w[3]);
-}
+// Gathers kept in flight per wave in stage 1 (eight row segments of S).
+constexpr int kUnroll1 = 8;
 
 // Stage 1 (left SpMM into the block-transposed layout).
 //   grid.x = row block within the chunk, grid.y = column tile of 64*VW columns;
@@ -115,19 +68,21 @@ __device__ inline void store_rows<uint16_t, 8>(uint16_t *dst, const float *v) {
 //   and broadcast lane by lane (readlane), so gathers never wait on index loads.
 //   Set a: Za[i,:] = rsa[i] * sum_e wa[e] S[col[e],:]          (wa/rsa may be null = 1)
 //   Set b: Zb[i,:] = sum_e csb[col[e]] S[col[e],:]            (only when TWO)
-template <typename TS, typename TZ, bool TWO, int VW, int RW>
+template <typename TS, bool TWO, int VW, int RW>
 __global__ __launch_bounds__(64 * 64 / RW) void k_stage1(const int64_t *__restrict__ rowptr,
                                                 const int32_t *__restrict__ col,
                                                 const float *__restrict__ wa, const float *__restrict__ rsa,
                                                 const float *__restrict__ csb,
                                                 const TS *__restrict__ S, int32_t n2, int32_t row0,
-                                                int32_t nrows, TZ *__restrict__ Za, TZ *__restrict__ Zb) {
+                                                int32_t nrows, float *__restrict__ Za, float *__restrict__ Zb) {
   const int lane = threadIdx.x & 63;
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int blk = blockIdx.x;
   const int c = blockIdx.y * (64 * VW) + lane * VW;
-  const bool valid = c < n2;
-  const TS *Sc = S + (valid ? c : 0);
+  // Lanes past the last column read column 0 instead (always in bounds) and their
+  // sums are never stored, so the gathers need no per-lane branch: a branch around
+  // each load would make the wave wait for it before the next one issues.
+  const TS *Sc = S + (c < n2 ? c : 0);
   float za[RW][VW], zb[RW][VW];
 #pragma unroll
   for (int rr = 0; rr < RW; ++rr) {
@@ -148,19 +103,15 @@ __global__ __launch_bounds__(64 * 64 / RW) void k_stage1(const int64_t *__restri
           if (TWO) my_b = csb[my_k];
         }
         int u = 0;
-        for (; u + 4 <= cnt; u += 4) {
-          float sv[4][VW];
+        for (; u + kUnroll1 <= cnt; u += kUnroll1) {
+          float sv[kUnroll1][VW];
 #pragma unroll
-          for (int q = 0; q < 4; ++q) {
+          for (int q = 0; q < kUnroll1; ++q) {
             const int k = bcast_i(my_k, u + q);
-            if (valid)
-              VLoad<TS, VW>::run(Sc + static_cast<int64_t>(k) * n2, sv[q]);
-            else
-#pragma unroll
-              for (int v = 0; v < VW; ++v) sv[q][v] = 0.f;
+            VLoad<TS, VW>::run(Sc + static_cast<int64_t>(k) * n2, sv[q]);
           }
 #pragma unroll
-          for (int q = 0; q < 4; ++q) {
+          for (int q = 0; q < kUnroll1; ++q) {
             const float fa = bcast_f(my_a, u + q);
             const float fb = TWO ? bcast_f(my_b, u + q) : 0.f;
 #pragma unroll
@@ -173,11 +124,7 @@ __global__ __launch_bounds__(64 * 64 / RW) void k_stage1(const int64_t *__restri
         for (; u < cnt; ++u) {
           const int k = bcast_i(my_k, u);
           float sv[VW];
-          if (valid)
-            VLoad<TS, VW>::run(Sc + static_cast<int64_t>(k) * n2, sv);
-          else
-#pragma unroll
-            for (int v = 0; v < VW; ++v) sv[v] = 0.f;
+          VLoad<TS, VW>::run(Sc + static_cast<int64_t>(k) * n2, sv);
           const float fa = bcast_f(my_a, u);
           const float fb = TWO ? bcast_f(my_b, u) : 0.f;
 #pragma unroll
@@ -199,19 +146,38 @@ __global__ __launch_bounds__(64 * 64 / RW) void k_stage1(const int64_t *__restri
       zb[rr][v] = b[v];
     }
   }
-  if (!valid) return;
-  // Each lane writes RW consecutive rows of each of its VW columns.
+  // Write the 64-row block transposed through LDS so that every 64-row column
+  // segment leaves as whole 128-byte lines.  The buffer holds NL columns; with
+  // VW = 4 the lanes take two turns (lanes 0-31, then 32-63), which keeps the
+  // buffer at 34 KB and four workgroups per CU resident.
+  constexpr int NL = VW >= 2 ? 128 : 64;            // columns staged per turn
+  constexpr int LP = NL / VW;                       // lanes per turn
+  constexpr int LS = kZtRows + 4;                   // padded column stride keeps float4 alignment
+  __shared__ float lds[NL * LS];
+  const int ct = blockIdx.y * (64 * VW);
   const int64_t base = static_cast<int64_t>(blk) * n2;
-  float t[RW];
 #pragma unroll
-  for (int v = 0; v < VW; ++v) {
+  for (int set = 0; set < (TWO ? 2 : 1); ++set) {
+    float *Z = set ? Zb : Za;
 #pragma unroll
-    for (int rr = 0; rr < RW; ++rr) t[rr] = za[rr][v];
-    store_rows<TZ, RW>(Za + (base + c + v) * kZtRows + w * RW, t);
-    if (TWO) {
+    for (int turn = 0; turn < 64 / LP; ++turn) {
+      __syncthreads();
+      if (lane / LP == turn) {
+        const int lc = (lane % LP) * VW;
 #pragma unroll
-      for (int rr = 0; rr < RW; ++rr) t[rr] = zb[rr][v];
-      store_rows<TZ, RW>(Zb + (base + c + v) * kZtRows + w * RW, t);
+        for (int v = 0; v < VW; ++v)
+#pragma unroll
+          for (int rr = 0; rr < RW; ++rr) lds[(lc + v) * LS + w * RW + rr] = set ? zb[rr][v] : za[rr][v];
+      }
+      __syncthreads();
+      const int c0 = ct + turn * NL;
+      for (int q = threadIdx.x; q < NL * (kZtRows / 4); q += blockDim.x) {
+        const int cl = q / (kZtRows / 4), part = q % (kZtRows / 4);
+        if (c0 + cl < n2) {
+          const float4 val = *reinterpret_cast<const float4 *>(&lds[cl * LS + part * 4]);
+          *reinterpret_cast<float4 *>(Z + (base + c0 + cl) * kZtRows + part * 4) = val;
+        }
+      }
     }
   }
 }
@@ -238,12 +204,12 @@ __device__ inline double log_accurate(float x) {
 //          (E, P accumulated in FP64; the tile of results is kept in FP64 until the
 //          epilogue rounds the assembled cost once)
 //   PLAIN: out[i,j] = rs[j] * sum_e Za[:,col e]
-template <typename TZ, bool COST>
+template <bool COST>
 __global__ __launch_bounds__(512) void k_stage2(const int64_t *__restrict__ rowptr,
                                                 const int32_t *__restrict__ col,
                                                 const float *__restrict__ w2a, const float *__restrict__ cs2b,
-                                                const float *__restrict__ rs, const TZ *__restrict__ Za,
-                                                const TZ *__restrict__ Zb, int32_t n2, int32_t row0,
+                                                const float *__restrict__ rs, const float *__restrict__ Za,
+                                                const float *__restrict__ Zb, int32_t n2, int32_t row0,
                                                 int32_t nrows, const float *__restrict__ C_node,
                                                 const int32_t *__restrict__ partner,
                                                 const double *__restrict__ a, const double *__restrict__ b,
@@ -253,14 +219,11 @@ __global__ __launch_bounds__(512) void k_stage2(const int64_t *__restrict__ rowp
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int j0 = blockIdx.x * 64;
   const int blk = blockIdx.y;
-  const TZ *za = Za + static_cast<int64_t>(blk) * n2 * kZtRows + lane;
-  const TZ *zb = COST ? Zb + static_cast<int64_t>(blk) * n2 * kZtRows + lane : nullptr;
+  const float *za = Za + static_cast<int64_t>(blk) * n2 * kZtRows + lane;
+  const float *zb = COST ? Zb + static_cast<int64_t>(blk) * n2 * kZtRows + lane : nullptr;
   for (int jj = 0; jj < 8; ++jj) {
     const int j = j0 + w * 8 + jj;
-    // per lane: FP32 -> one row (lane); BF16 -> two rows (2q, 2q+1) of every other
-    // neighbour (half-wave h), each lane loading 4 bytes
-    const int h = lane >> 5, q = lane & 31;
-    double E0 = 0.0, E1 = 0.0, P0 = 0.0, P1 = 0.0;
+    double E = 0.0, P = 0.0;
     if (j < n2) {
       const int64_t e0 = rowptr[j], e1 = rowptr[j + 1];
       for (int64_t base = e0; base < e1; base += 64) {
@@ -274,110 +237,45 @@ __global__ __launch_bounds__(512) void k_stage2(const int64_t *__restrict__ rowp
             my_c = cs2b[my_l];
           }
         }
-        if (sizeof(TZ) == 2) {
-          const uint32_t *ua = reinterpret_cast<const uint32_t *>(Za + static_cast<int64_t>(blk) * n2 * kZtRows) + q;
-          const uint32_t *ub =
-              COST ? reinterpret_cast<const uint32_t *>(Zb + static_cast<int64_t>(blk) * n2 * kZtRows) + q : nullptr;
-          for (int u = 0; u < cnt; u += 8) {
-            uint32_t xa[4], ya[4];
-            double wv[4], cv[4];
-            bool ok[4];
+        int u = 0;
+        for (; u + 4 <= cnt; u += 4) {
+          float x[4], y[4];
 #pragma unroll
-            for (int t = 0; t < 4; ++t) {
-              const int ua_ = u + 2 * t, ub_ = u + 2 * t + 1;
-              const int uu = h ? ub_ : ua_;
-              const int l0 = bcast_i(my_l, ua_ < 64 ? ua_ : 63), l1 = bcast_i(my_l, ub_ < 64 ? ub_ : 63);
-              const int l = h ? l1 : l0;
-              ok[t] = uu < cnt;
-              xa[t] = ok[t] ? ua[static_cast<int64_t>(l) * (kZtRows / 2)] : 0u;
-              if (COST) {
-                ya[t] = ok[t] ? ub[static_cast<int64_t>(l) * (kZtRows / 2)] : 0u;
-                const float w0 = bcast_f(my_w, ua_ < 64 ? ua_ : 63), w1 = bcast_f(my_w, ub_ < 64 ? ub_ : 63);
-                const float c0 = bcast_f(my_c, ua_ < 64 ? ua_ : 63), c1 = bcast_f(my_c, ub_ < 64 ? ub_ : 63);
-                wv[t] = static_cast<double>(h ? w1 : w0);
-                cv[t] = static_cast<double>(h ? c1 : c0);
-              }
-            }
-#pragma unroll
-            for (int t = 0; t < 4; ++t) {
-              if (!ok[t]) continue;
-              const double x0 = static_cast<double>(__uint_as_float(xa[t] << 16));
-              const double x1 = static_cast<double>(__uint_as_float(xa[t] & 0xffff0000u));
-              if (COST) {
-                E0 = fma(wv[t], x0, E0);
-                E1 = fma(wv[t], x1, E1);
-                P0 = fma(cv[t], static_cast<double>(__uint_as_float(ya[t] << 16)), P0);
-                P1 = fma(cv[t], static_cast<double>(__uint_as_float(ya[t] & 0xffff0000u)), P1);
-              } else {
-                E0 += x0;
-                E1 += x1;
-              }
-            }
+          for (int t = 0; t < 4; ++t) {
+            const int64_t l = bcast_i(my_l, u + t);
+            x[t] = za[l * kZtRows];
+            if (COST) y[t] = zb[l * kZtRows];
           }
-        } else {
-          int u = 0;
-          for (; u + 4 <= cnt; u += 4) {
-            float x[4], y[4];
 #pragma unroll
-            for (int t = 0; t < 4; ++t) {
-              const int64_t l = bcast_i(my_l, u + t);
-              x[t] = load_as_f32<TZ>(za, l * kZtRows);
-              if (COST) y[t] = load_as_f32<TZ>(zb, l * kZtRows);
-            }
-#pragma unroll
-            for (int t = 0; t < 4; ++t) {
-              if (COST) {
-                E0 = fma(static_cast<double>(bcast_f(my_w, u + t)), static_cast<double>(x[t]), E0);
-                P0 = fma(static_cast<double>(bcast_f(my_c, u + t)), static_cast<double>(y[t]), P0);
-              } else {
-                E0 += static_cast<double>(x[t]);
-              }
-            }
-          }
-          for (; u < cnt; ++u) {
-            const int64_t l = bcast_i(my_l, u);
-            const float x = load_as_f32<TZ>(za, l * kZtRows);
+          for (int t = 0; t < 4; ++t) {
             if (COST) {
-              E0 = fma(static_cast<double>(bcast_f(my_w, u)), static_cast<double>(x), E0);
-              P0 = fma(static_cast<double>(bcast_f(my_c, u)), static_cast<double>(load_as_f32<TZ>(zb, l * kZtRows)), P0);
+              E = fma(static_cast<double>(bcast_f(my_w, u + t)), static_cast<double>(x[t]), E);
+              P = fma(static_cast<double>(bcast_f(my_c, u + t)), static_cast<double>(y[t]), P);
             } else {
-              E0 += static_cast<double>(x);
+              E += static_cast<double>(x[t]);
             }
           }
         }
-      }
-    }
-    if (sizeof(TZ) == 2) {
-      E0 += __shfl_xor(E0, 32, 64);
-      E1 += __shfl_xor(E1, 32, 64);
-      if (COST) {
-        P0 += __shfl_xor(P0, 32, 64);
-        P1 += __shfl_xor(P1, 32, 64);
-      }
-      if (h == 0) {
-        double g0 = 0.0, g1 = 0.0;
-        if (j < n2) {
+        for (; u < cnt; ++u) {
+          const int64_t l = bcast_i(my_l, u);
+          const float x = za[l * kZtRows];
           if (COST) {
-            g0 = cf.le * E0 - cf.ln * log_accurate(static_cast<float>(P0 + cf.delta));
-            g1 = cf.le * E1 - cf.ln * log_accurate(static_cast<float>(P1 + cf.delta));
+            E = fma(static_cast<double>(bcast_f(my_w, u)), static_cast<double>(x), E);
+            P = fma(static_cast<double>(bcast_f(my_c, u)), static_cast<double>(zb[l * kZtRows]), P);
           } else {
-            g0 = static_cast<double>(rs[j]) * E0;
-            g1 = static_cast<double>(rs[j]) * E1;
+            E += static_cast<double>(x);
           }
         }
-        tile[2 * q][w * 8 + jj] = g0;
-        tile[2 * q + 1][w * 8 + jj] = g1;
       }
-    } else {
-      double g = 0.0;
-      if (j < n2) {
-        if (COST)
-          g = cf.le * E0 - cf.ln * log_accurate(static_cast<float>(P0 + cf.delta));
-        else
-          g = static_cast<double>(rs[j]) * E0;
-      }
-      tile[lane][w * 8 + jj] = g;
     }
+    double g = 0.0;
+    if (j < n2) {
+      if (COST)
+        g = cf.le * E - cf.ln * log_accurate(static_cast<float>(P + cf.delta));
+      else
+        g = static_cast<double>(rs[j]) * E;
+    }
+    tile[lane][w * 8 + jj] = g;
   }
   __syncthreads();
   const int j = j0 + lane;
@@ -392,22 +290,22 @@ __global__ __launch_bounds__(512) void k_stage2(const int64_t *__restrict__ rowp
     const double g = tile[r][lane];
     if (COST) {
       const double anc = partner[i] == j ? cf.anc_on : cf.anc_off;
-      const double v = static_cast<double>(C_node[idx]) + g + cf.la * anc +
-                       cf.kp * (static_cast<double>(out[idx]) - aj - b[i]);
-      out[idx] = static_cast<float>(v);
+      const double v = static_cast<double>(ld_stream(C_node + idx)) + g + cf.la * anc +
+                       cf.kp * (static_cast<double>(ld_stream(out + idx)) - aj - b[i]);
+      st_stream(out + idx, static_cast<float>(v));
     } else {
-      out[idx] = static_cast<float>(g);
+      st_stream(out + idx, static_cast<float>(g));
     }
   }
 }
 
-template <typename TS, typename TZ>
+template <typename TS>
 static int cost_chunks(const CostArgs &c, int32_t chunk_rows, void *zt, hipStream_t s, KTimer *tm) {
   const int32_t n1 = c.A1->n, n2 = c.A2->n;
   const size_t nblk_max = (static_cast<size_t>(chunk_rows) + kZtRows - 1) / kZtRows;
-  TZ *Za = static_cast<TZ *>(zt);
-  TZ *Zb = reinterpret_cast<TZ *>(static_cast<char *>(zt) +
-                                  align_up(nblk_max * kZtRows * static_cast<size_t>(n2) * sizeof(TZ), 256));
+  float *Za = static_cast<float *>(zt);
+  float *Zb = reinterpret_cast<float *>(static_cast<char *>(zt) +
+                                        align_up(nblk_max * kZtRows * static_cast<size_t>(n2) * sizeof(float), 256));
   CostCoef cf;
   cf.le = c.lambda_e;
   cf.ln = c.lambda_n;
@@ -419,33 +317,30 @@ static int cost_chunks(const CostArgs &c, int32_t chunk_rows, void *zt, hipStrea
   for (int32_t r0 = 0; r0 < n1; r0 += chunk_rows) {
     const int32_t nr = n1 - r0 < chunk_rows ? n1 - r0 : chunk_rows;
     const int nblk = ceil_div(nr, kZtRows);
-    constexpr int VW = sizeof(TS) == 2 ? 4 : 2;
-    constexpr int RW = sizeof(TS) == 2 ? 4 : 8;  // keeps the accumulators near 32 registers
+    // two columns per lane (8-byte FP32 or 4-byte BF16 loads), eight rows per wave:
+    // 32 accumulators and eight gathers in flight per wave at full occupancy
+    constexpr int VW = 2, RW = 8;
     if (n2 % VW == 0)
       FA_TIMED(tm, KK_STAGE1, s,
-               FA_LAUNCH((k_stage1<TS, TZ, true, VW, RW>), dim3(nblk, ceil_div(n2, 64 * VW)), dim3(64 * 64 / RW), 0, s,
+               FA_LAUNCH((k_stage1<TS, true, VW, RW>), dim3(nblk, ceil_div(n2, 64 * VW)), dim3(64 * 64 / RW), 0, s,
                          c.A1->rowptr, c.A1->colidx, c.w1, nullptr, c.inv1, static_cast<const TS *>(c.S), n2, r0, nr,
                          Za, Zb));
     else
       FA_TIMED(tm, KK_STAGE1, s,
-               FA_LAUNCH((k_stage1<TS, TZ, true, 1, 8>), dim3(nblk, ceil_div(n2, 64)), dim3(512), 0, s, c.A1->rowptr,
+               FA_LAUNCH((k_stage1<TS, true, 1, 8>), dim3(nblk, ceil_div(n2, 64)), dim3(512), 0, s, c.A1->rowptr,
                          c.A1->colidx, c.w1, nullptr, c.inv1, static_cast<const TS *>(c.S), n2, r0, nr, Za, Zb));
     FA_TIMED(tm, KK_STAGE2, s,
-             FA_LAUNCH((k_stage2<TZ, true>), dim3(ceil_div(n2, 64), nblk), dim3(512), 0, s, c.A2->rowptr,
+             FA_LAUNCH((k_stage2<true>), dim3(ceil_div(n2, 64), nblk), dim3(512), 0, s, c.A2->rowptr,
                        c.A2->colidx, c.w2, c.inv2, nullptr, Za, Zb, n2, r0, nr, c.C_node, c.partner, c.a, c.b, cf,
                        c.C));
   }
   return FA_OK;
 }
 
-int run_cost(const CostArgs &c, int32_t chunk_rows, int32_t zdt, void *zt, hipStream_t s, KTimer *tm) {
+int run_cost(const CostArgs &c, int32_t chunk_rows, void *zt, hipStream_t s, KTimer *tm) {
   if (c.A1->n == 0 || c.A2->n == 0) return FA_OK;
-  if (c.s_dtype == FA_BF16) {
-    if (zdt == FA_BF16) return cost_chunks<uint16_t, uint16_t>(c, chunk_rows, zt, s, tm);
-    return cost_chunks<uint16_t, float>(c, chunk_rows, zt, s, tm);
-  }
-  if (zdt == FA_BF16) return cost_chunks<float, uint16_t>(c, chunk_rows, zt, s, tm);
-  return cost_chunks<float, float>(c, chunk_rows, zt, s, tm);
+  if (c.s_dtype == FA_BF16) return cost_chunks<uint16_t>(c, chunk_rows, zt, s, tm);
+  return cost_chunks<float>(c, chunk_rows, zt, s, tm);
 }
 
 // k times C <- Abar1 C Abar2^T.  Stage 1 reads every row of C, so each step
@@ -462,12 +357,12 @@ int run_propagate(const fa_csr *A1, const float *inv1, const fa_csr *A2, const f
       const int32_t nr = n1 - r0 < chunk_rows ? n1 - r0 : chunk_rows;
       const int nblk = ceil_div(nr, kZtRows);
       if (n2 % 2 == 0)
-        FA_LAUNCH((k_stage1<float, float, false, 2, 8>), dim3(nblk, ceil_div(n2, 128)), dim3(512), 0, s, A1->rowptr,
+        FA_LAUNCH((k_stage1<float, false, 2, 8>), dim3(nblk, ceil_div(n2, 128)), dim3(512), 0, s, A1->rowptr,
                   A1->colidx, nullptr, inv1, nullptr, src, n2, r0, nr, Z, nullptr);
       else
-        FA_LAUNCH((k_stage1<float, float, false, 1, 8>), dim3(nblk, ceil_div(n2, 64)), dim3(512), 0, s, A1->rowptr,
+        FA_LAUNCH((k_stage1<float, false, 1, 8>), dim3(nblk, ceil_div(n2, 64)), dim3(512), 0, s, A1->rowptr,
                   A1->colidx, nullptr, inv1, nullptr, src, n2, r0, nr, Z, nullptr);
-      FA_LAUNCH((k_stage2<float, false>), dim3(ceil_div(n2, 64), nblk), dim3(512), 0, s, A2->rowptr,
+      FA_LAUNCH((k_stage2<false>), dim3(ceil_div(n2, 64), nblk), dim3(512), 0, s, A2->rowptr,
                 A2->colidx, nullptr, nullptr, inv2, Z, nullptr, n2, r0, nr, nullptr, nullptr, nullptr,
                 nullptr, cf, dst);
     }
@@ -490,7 +385,8 @@ static int resolve_chunk(int32_t n1, int32_t chunk_rows) {
 
 extern "C" size_t fa_cost_workspace_size(int32_t n1, int32_t n2, int32_t plan_dtype, int32_t chunk_rows) {
   if (n1 <= 0 || n2 <= 0) return 0;
-  return zt_bytes(resolve_chunk(n1, chunk_rows), n2, plan_dtype == FA_BF16 ? FA_BF16 : FA_F32);
+  (void)plan_dtype;  // the intermediate is FP32 in both forms
+  return zt_bytes(resolve_chunk(n1, chunk_rows), n2);
 }
 
 extern "C" int fa_propagate(const fa_csr *A1, const float *inv_deg1, const fa_csr *A2, const float *inv_deg2,
@@ -503,8 +399,8 @@ extern "C" int fa_propagate(const fa_csr *A1, const float *inv_deg1, const fa_cs
   if (n1 == 0 || n2 == 0 || k == 0) return FA_OK;
   FA_REQUIRE(C && C_tmp && inv_deg1 && inv_deg2, FA_ERR_ARG, "fa_propagate: null pointer");
   const int32_t cr = resolve_chunk(n1, chunk_rows);
-  FA_REQUIRE(ws && ws_bytes >= zt_bytes(cr, n2, FA_F32), FA_ERR_WORKSPACE,
-             "fa_propagate: workspace %zu < %zu bytes", ws_bytes, zt_bytes(cr, n2, FA_F32));
+  FA_REQUIRE(ws && ws_bytes >= zt_bytes(cr, n2), FA_ERR_WORKSPACE,
+             "fa_propagate: workspace %zu < %zu bytes", ws_bytes, zt_bytes(cr, n2));
   return run_propagate(A1, inv_deg1, A2, inv_deg2, C, C_tmp, k, cr, ws, static_cast<hipStream_t>(stream));
 }
 
@@ -522,10 +418,10 @@ extern "C" int fa_cost(const fa_csr *A1, const fa_csr *A2, const float *w1, cons
   FA_REQUIRE(S && C_node && partner && a && b && C_inout && inv_deg1 && inv_deg2, FA_ERR_ARG, "fa_cost: null pointer");
   FA_REQUIRE((A1->nnz == 0 || w1) && (A2->nnz == 0 || w2), FA_ERR_ARG, "fa_cost: null C1/C2 values");
   const int32_t cr = resolve_chunk(n1, p->chunk_rows);
-  const size_t need = zt_bytes(cr, n2, s_dtype);
+  const size_t need = zt_bytes(cr, n2);
   FA_REQUIRE(ws && ws_bytes >= need, FA_ERR_WORKSPACE, "fa_cost: workspace %zu < %zu bytes", ws_bytes, need);
   hipStream_t s = static_cast<hipStream_t>(stream);
   CostArgs c{A1, A2, w1, inv_deg1, w2, inv_deg2, S, s_dtype, C_node, partner, a, b,
              p->lambda_e, p->lambda_n, p->lambda_a, p->lambda_p, p->eps, p->eps_anchor, p->delta_nbr, C_inout};
-  return run_cost(c, cr, s_dtype, ws, s);
+  return run_cost(c, cr, ws, s);
 }

@@ -13,10 +13,12 @@ backward (fa_mlp_backward) and the update (fa_adam_step) all run in the HIP
 library; PyTorch only holds the buffers and draws minibatch indices.
 
 Evaluation: on held-out pairs, the first inner solve from the learned start vs
-from zero - marginal error after K iterations and the iterations the learned
-start needs to reach the cold solve's final error.
+from zero - marginal error after K iterations, the iterations the learned start
+needs to reach the cold solve's final error, and the iterations both need to
+reach a fixed tolerance (with the argmax agreement of the two plans there).
 
 Usage: python -m paper_2607_11952_amd.train_warm --pairs 2000 --out <weights>
+       python -m paper_2607_11952_amd.train_warm --eval-only --weights <weights>
 """
 from __future__ import annotations
 
@@ -102,7 +104,7 @@ def train(F: torch.Tensor, t: torch.Tensor, epochs: int, batch: int, lr: float, 
     return prm, hist
 
 
-def evaluate(prm: torch.Tensor, seeds, n: int, K: int, device, log=print):
+def evaluate(prm: torch.Tensor, seeds, n: int, K: int, device, log=print, tol: float = 1e-6, cap: int = 1000):
     rows = []
     for s in seeds:
         pr = make_pair(family(s, n))
@@ -113,11 +115,33 @@ def evaluate(prm: torch.Tensor, seeds, n: int, K: int, device, log=print):
         hit = first_solve(inp, K, mlp=prm, tol=e_cold)
         it_warm = int(hit.stats.inner_iters[0])
         agree = float((warm_.argmax == cold.argmax).float().mean())
-        rows.append(dict(seed=s, n=n, err_cold=e_cold, err_warm=e_warm, iters_warm_to_cold_err=it_warm,
-                         argmax_agreement=agree))
+        # both starts run to the same tolerance (capped)
+        ct = first_solve(inp, cap, tol=tol)
+        ct_it, ct_err, ct_arg = int(ct.stats.inner_iters[0]), float(ct.stats.inner_err[0]), ct.argmax.clone()
+        wt = first_solve(inp, cap, mlp=prm, tol=tol)
+        wt_it, wt_err = int(wt.stats.inner_iters[0]), float(wt.stats.inner_err[0])
+        agree_tol = float((wt.argmax == ct_arg).float().mean())
+        rows.append(dict(seed=s, n=n, K=K, err_cold=e_cold, err_warm=e_warm, iters_warm_to_cold_err=it_warm,
+                         argmax_agreement=agree, tol=tol, cap=cap, iters_cold_to_tol=ct_it, err_cold_at_stop=ct_err,
+                         iters_warm_to_tol=wt_it, err_warm_at_stop=wt_err, argmax_agreement_at_tol=agree_tol))
         log(f"[eval] seed {s}: err after {K}: cold {e_cold:.3e} warm {e_warm:.3e}; warm reaches the cold error in "
-            f"{it_warm} iterations; argmax agreement {agree:.4f}")
+            f"{it_warm} iterations; argmax agreement {agree:.4f}; to {tol:g}: cold {ct_it} ({ct_err:.2e}) "
+            f"warm {wt_it} ({wt_err:.2e}), agreement {agree_tol:.4f}")
     return rows
+
+
+def summarize(rows):
+    f = lambda k: [r[k] for r in rows]
+    ic, iw = np.array(f("iters_cold_to_tol"), float), np.array(f("iters_warm_to_tol"), float)
+    return dict(pairs=len(rows), mean_err_cold=float(np.mean(f("err_cold"))), mean_err_warm=float(np.mean(f("err_warm"))),
+                median_err_ratio=float(np.median(np.array(f("err_cold")) / np.maximum(f("err_warm"), 1e-300))),
+                mean_iters_warm_to_cold_err=float(np.mean(f("iters_warm_to_cold_err"))),
+                # K cold iterations buy the error the learned start reaches in this many fewer
+                speedup_to_cold_err=float(len(rows) * rows[0]["K"] / max(sum(f("iters_warm_to_cold_err")), 1)),
+                mean_iters_cold_to_tol=float(ic.mean()), mean_iters_warm_to_tol=float(iw.mean()),
+                iteration_ratio=float(ic.sum() / max(iw.sum(), 1.0)),
+                min_argmax_agreement_at_tol=float(np.min(f("argmax_agreement_at_tol"))),
+                mean_argmax_agreement_at_tol=float(np.mean(f("argmax_agreement_at_tol"))))
 
 
 def main():
@@ -130,12 +154,27 @@ def main():
     ap.add_argument("--eval-pairs", type=int, default=8)
     ap.add_argument("--eval-n", type=int, default=20000)
     ap.add_argument("--eval-k", type=int, default=100)
+    ap.add_argument("--eval-seed0", type=int, default=5000)
+    ap.add_argument("--tol", type=float, default=1e-6)
+    ap.add_argument("--cap", type=int, default=1000)
     ap.add_argument("--out", default=warm.WEIGHTS)
     ap.add_argument("--report", default="")
+    ap.add_argument("--eval-only", action="store_true", help="evaluate --weights, no training")
+    ap.add_argument("--weights", default=warm.WEIGHTS)
     args = ap.parse_args()
     dev = torch.device("cuda:0")
     log = lambda m: print(m, file=sys.stderr, flush=True)
     t0 = time.time()
+    seeds = range(args.eval_seed0, args.eval_seed0 + args.eval_pairs)
+    if args.eval_only:
+        prm = torch.from_numpy(warm.read_weights(args.weights)).to(dev)
+        rows = evaluate(prm, seeds, args.eval_n, args.eval_k, dev, log=log, tol=args.tol, cap=args.cap)
+        summ = summarize(rows)
+        if args.report:
+            with open(args.report, "w") as f:
+                json.dump(dict(weights=args.weights, eval=rows, summary=summ, seconds=time.time() - t0), f, indent=1)
+        print(json.dumps(summ))
+        return
     Fs, ts, errs = [], [], []
     for k in range(args.pairs):
         F, t, e = pair_data(1000 + k, args.inner, dev)
@@ -151,16 +190,14 @@ def main():
     prm, hist = train(F, t, args.epochs, args.batch, args.lr, log=log)
     warm.save_weights(prm.cpu().numpy(), args.out)
     log(f"[train] saved {args.out}")
-    rows = evaluate(prm, range(5000, 5000 + args.eval_pairs), args.eval_n, args.eval_k, dev, log=log)
+    rows = evaluate(prm, seeds, args.eval_n, args.eval_k, dev, log=log, tol=args.tol, cap=args.cap)
+    summ = summarize(rows)
     rep = dict(pairs=args.pairs, nodes=int(F.shape[0]), target_var=float(t.var()), mse_per_epoch=hist,
-               eval=rows, seconds=time.time() - t0)
+               eval=rows, summary=summ, seconds=time.time() - t0)
     if args.report:
         with open(args.report, "w") as f:
             json.dump(rep, f, indent=1)
-    print(json.dumps(dict(final_mse=hist[-1], target_var=float(t.var()),
-                          mean_err_cold=float(np.mean([r["err_cold"] for r in rows])),
-                          mean_err_warm=float(np.mean([r["err_warm"] for r in rows])),
-                          mean_iters_warm=float(np.mean([r["iters_warm_to_cold_err"] for r in rows])))))
+    print(json.dumps(dict(final_mse=hist[-1], target_var=float(t.var()), **summ)))
 
 
 if __name__ == "__main__":

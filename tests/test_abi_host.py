@@ -73,6 +73,8 @@ def test_default_params_and_sizes(lib):
     assert lib.raw("fa_sinkhorn_workspace_size")(1000, 1000) > 0
     n = lib.raw("fa_align_workspace_size")(1000, 900, 32, 100, 8000, 7000, p)
     assert n > 2 * 1000 * 900 * 4
-    p.plan_dtype = binding.FA_BF16
-    assert lib.raw("fa_cost_workspace_size")(1000, 900, binding.FA_BF16, 0) < \
-        lib.raw("fa_cost_workspace_size")(1000, 900, binding.FA_F32, 0)
+    # two FP32 intermediates of ceil(rows/64)*64 x n2, whatever the plan's dtype
+    want = 2 * 1024 * 900 * 4
+    for dt in (binding.FA_F32, binding.FA_BF16):
+        assert lib.raw("fa_cost_workspace_size")(1000, 900, dt, 0) == want
+    assert lib.raw("fa_cost_workspace_size")(1000, 900, binding.FA_F32, 100) == 2 * 128 * 900 * 4
