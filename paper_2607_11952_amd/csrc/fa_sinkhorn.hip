@@ -38,8 +38,9 @@ static SinkLayout sink_layout(int32_t n1, int32_t n2) {
   SinkLayout L;
   L.V = (n2 % 4 == 0) ? 4 : 1;
   L.ncolblk = ceil_div(n2, 256 * L.V);
-  // about eight rounds of resident workgroups, so the last round's tail is short
-  int want = ceil_div(16384, L.ncolblk > 0 ? L.ncolblk : 1);
+  // about 8192 workgroups (four to five rounds of resident ones): long enough row
+  // ranges per workgroup to keep the streams sequential, short enough tail
+  int want = ceil_div(8192, L.ncolblk > 0 ? L.ncolblk : 1);
   int maxs = n1 / 16 > 1 ? n1 / 16 : 1;
   L.nsplit = want < 1 ? 1 : (want > maxs ? maxs : want);
   L.rows_per_split = ceil_div(n1 > 0 ? n1 : 1, L.nsplit);
@@ -89,6 +90,21 @@ struct Vec<4> {
   }
 };
 
+template <>
+struct Vec<8> {
+  static __device__ inline void load(const float *p, float *o) {
+    const f32x4 t = ld_stream4(p), u = ld_stream4(p + 4);
+    o[0] = t.x;
+    o[1] = t.y;
+    o[2] = t.z;
+    o[3] = t.w;
+    o[4] = u.x;
+    o[5] = u.y;
+    o[6] = u.z;
+    o[7] = u.w;
+  }
+};
+
 // Vector store of V consecutive plan entries (one 16-byte FP32 or 8-byte BF16
 // store per lane for V = 4).
 template <typename T, int V>
@@ -113,9 +129,12 @@ struct VStore<uint16_t, 4> {
   }
 };
 
+// Rows of C in flight per thread and step of the column pass.
+constexpr int kColRowsPerStep = 4;
+
 // Column pass, part 1: per (column strip, row range) partial LSE of
 // y_ij = (a_j + b_i - C_ij) * log2(e)/eps over the rows of the range.
-template <int V>
+template <int V, int U>
 __global__ __launch_bounds__(256) void k_lse_col_partial(const float *__restrict__ C, int32_t n1, int32_t n2,
                                                          const double *__restrict__ bufA0,
                                                          const double *__restrict__ bufA1, int32_t cur,
@@ -137,22 +156,24 @@ __global__ __launch_bounds__(256) void k_lse_col_partial(const float *__restrict
     m[v] = -INFINITY;
     s[v] = 0.0;
   }
-  constexpr int U = 4;
   for (int i = r0; i < r1; i += U) {
-    double x[U][V];
+    // All U row loads are issued before any is used (no branch around a load, so
+    // none waits for the previous one); rows past the range re-read row r1-1 and
+    // are masked to -inf.
+    float c[U][V];
+    double bk[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      if (i + u < r1) {
-        const double bk = b[i + u] * k2;
-        float c[V];
-        Vec<V>::load(C + static_cast<int64_t>(i + u) * n2 + j, c);
-#pragma unroll
-        for (int v = 0; v < V; ++v) x[u][v] = fma(-static_cast<double>(c[v]), k2, ak[v] + bk);
-      } else {
-#pragma unroll
-        for (int v = 0; v < V; ++v) x[u][v] = -INFINITY;
-      }
+      const int iu = min(i + u, r1 - 1);
+      Vec<V>::load(C + static_cast<int64_t>(iu) * n2 + j, c[u]);
+      bk[u] = b[iu] * k2;
     }
+    double x[U][V];
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int v = 0; v < V; ++v)
+        x[u][v] = (i + u < r1) ? fma(-static_cast<double>(c[u][v]), k2, ak[v] + bk[u]) : -INFINITY;
 #pragma unroll
     for (int v = 0; v < V; ++v) {
       double mx = x[0][v];
@@ -237,15 +258,15 @@ __global__ __launch_bounds__(256) void k_lse_col_merge(int32_t n2, int32_t nspli
   }
 }
 
-// Row pass (b-update): eight rows per workgroup, the a-values of a column chunk are
-// loaded once and reused for the eight rows.
-template <int V>
+// Row pass (b-update): R rows per workgroup, the a-values of a column chunk are
+// loaded once and reused for the R rows.
+constexpr int kRowsPerWg = 8;
+template <int V, int R>
 __global__ __launch_bounds__(256) void k_lse_row(const float *__restrict__ C, int32_t n1, int32_t n2,
                                                  const double *__restrict__ bufA0, const double *__restrict__ bufA1,
                                                  int32_t nxt, double *__restrict__ b, double k2, double eps,
                                                  double log_mu, const SinkCtl *__restrict__ ctl) {
   if (ctl->done) return;
-  constexpr int R = 8;
   const double *a = nxt ? bufA1 : bufA0;
   const int i0 = blockIdx.x * R;
   double bk[R], m[R], s[R];
@@ -256,14 +277,16 @@ __global__ __launch_bounds__(256) void k_lse_row(const float *__restrict__ C, in
     s[r] = 0.0;
   }
   for (int j = threadIdx.x * V; j < n2; j += 256 * V) {
+    // the R row loads go out together; rows past n1 re-read row n1-1, their sums are dropped
+    float cr[R][V];
+#pragma unroll
+    for (int r = 0; r < R; ++r) Vec<V>::load(C + static_cast<int64_t>(min(i0 + r, n1 - 1)) * n2 + j, cr[r]);
     double ak[V];
 #pragma unroll
     for (int v = 0; v < V; ++v) ak[v] = a[j + v] * k2;
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-      if (i0 + r >= n1) continue;
-      float c[V];
-      Vec<V>::load(C + static_cast<int64_t>(i0 + r) * n2 + j, c);
+      const float *c = cr[r];
       double x[V];
       double mx = -INFINITY;
 #pragma unroll
@@ -331,18 +354,18 @@ int run_sinkhorn(const float *C, int32_t n1, int32_t n2, double eps, double *a, 
   const double log_nu = -log(static_cast<double>(n2)), nu = 1.0 / n2;
   const double log_mu = -log(static_cast<double>(n1));
   FA_LAUNCH(k_sink_reset, dim3(1), dim3(1), 0, s, ctl);
-  const dim3 gcol(L.ncolblk, L.nsplit), gmerge(L.nmerge), grow(ceil_div(n1, 8));
+  const dim3 gcol(L.ncolblk, L.nsplit), gmerge(L.nmerge), grow(ceil_div(n1, kRowsPerWg));
   for (int it = 0; it <= max_iter; ++it) {
     const int cur = it & 1;
     const int is_final = it == max_iter;
     const int is_check = it > 0 && (it % check_every == 0);
     if (L.V == 4)
       FA_TIMED(tm, KK_COL_PARTIAL, s,
-               FA_LAUNCH(k_lse_col_partial<4>, gcol, dim3(256), 0, s, C, n1, n2, a, w.a_next, cur, b, k2,
+               FA_LAUNCH((k_lse_col_partial<4, kColRowsPerStep>), gcol, dim3(256), 0, s, C, n1, n2, a, w.a_next, cur, b, k2,
                          L.rows_per_split, w.pm, w.ps, ctl));
     else
       FA_TIMED(tm, KK_COL_PARTIAL, s,
-               FA_LAUNCH(k_lse_col_partial<1>, gcol, dim3(256), 0, s, C, n1, n2, a, w.a_next, cur, b, k2,
+               FA_LAUNCH((k_lse_col_partial<1, kColRowsPerStep>), gcol, dim3(256), 0, s, C, n1, n2, a, w.a_next, cur, b, k2,
                          L.rows_per_split, w.pm, w.ps, ctl));
     FA_TIMED(tm, KK_COL_MERGE, s,
              FA_LAUNCH(k_lse_col_merge, gmerge, dim3(256), 0, s, n2, L.nsplit, w.pm, w.ps, a, w.a_next, cur, eps,
@@ -350,11 +373,11 @@ int run_sinkhorn(const float *C, int32_t n1, int32_t n2, double eps, double *a, 
     if (is_final) break;
     if (L.V == 4)
       FA_TIMED(tm, KK_ROW, s,
-               FA_LAUNCH(k_lse_row<4>, grow, dim3(256), 0, s, C, n1, n2, a, w.a_next, 1 - cur, b, k2, eps, log_mu,
+               FA_LAUNCH((k_lse_row<4, kRowsPerWg>), grow, dim3(256), 0, s, C, n1, n2, a, w.a_next, 1 - cur, b, k2, eps, log_mu,
                          ctl));
     else
       FA_TIMED(tm, KK_ROW, s,
-               FA_LAUNCH(k_lse_row<1>, grow, dim3(256), 0, s, C, n1, n2, a, w.a_next, 1 - cur, b, k2, eps, log_mu,
+               FA_LAUNCH((k_lse_row<1, kRowsPerWg>), grow, dim3(256), 0, s, C, n1, n2, a, w.a_next, 1 - cur, b, k2, eps, log_mu,
                          ctl));
   }
   FA_LAUNCH(k_final_a, dim3(ceil_div(n2, 256)), dim3(256), 0, s, a, w.a_next, n2, ctl);
@@ -388,12 +411,15 @@ __global__ __launch_bounds__(256) void k_plan(const float *__restrict__ C, int32
     double ak[V];
 #pragma unroll
     for (int v = 0; v < V; ++v) ak[v] = a[j + v] * k2;
+    float cr[R][V];
+#pragma unroll
+    for (int r = 0; r < R; ++r) Vec<V>::load(C + static_cast<int64_t>(min(i0 + r, n1 - 1)) * n2 + j, cr[r]);
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       if (i0 + r >= n1) continue;
       const int64_t base = static_cast<int64_t>(i0 + r) * n2 + j;
-      float c[V], sv[V];
-      Vec<V>::load(C + base, c);
+      const float *c = cr[r];
+      float sv[V];
 #pragma unroll
       for (int v = 0; v < V; ++v) {
         const double y = fma(-static_cast<double>(c[v]), k2, ak[v] + bk[r]);
