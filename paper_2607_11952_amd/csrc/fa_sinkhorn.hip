@@ -41,10 +41,10 @@ static SinkLayout sink_layout(int32_t n1, int32_t n2) {
   // about 8192 workgroups (four to five rounds of resident ones): long enough row
   // ranges per workgroup to keep the streams sequential, short enough tail
   int want = ceil_div(8192, L.ncolblk > 0 ? L.ncolblk : 1);
-  int maxs = n1 / 16 > 1 ? n1 / 16 : 1;
+  int maxs = n1 / 64 > 1 ? n1 / 64 : 1;  // at least 64 rows per split: partials stay small next to C
   L.nsplit = want < 1 ? 1 : (want > maxs ? maxs : want);
   L.rows_per_split = ceil_div(n1 > 0 ? n1 : 1, L.nsplit);
-  L.nmerge = ceil_div(n2, 256);
+  L.nmerge = ceil_div(n2, 64);
   return L;
 }
 
@@ -196,9 +196,11 @@ __global__ __launch_bounds__(256) void k_lse_col_partial(const float *__restrict
   }
 }
 
-// Column pass, part 2: fold the partials of each column in split order, form the
+// Column pass, part 2: fold the partials of each column in a fixed order, form the
 // new a_j (into the other buffer) and the column's marginal violation; the last
 // workgroup to finish sums the violations in block order and applies the stop rule.
+// A workgroup takes 64 columns; four lanes per column fold every fourth split
+// each (one pass, online max), then lane group 0 folds the four results in order.
 __global__ __launch_bounds__(256) void k_lse_col_merge(int32_t n2, int32_t nsplit, const double *__restrict__ pm,
                                                        const double *__restrict__ ps, double *__restrict__ bufA0,
                                                        double *__restrict__ bufA1, int32_t cur, double eps,
@@ -209,16 +211,19 @@ __global__ __launch_bounds__(256) void k_lse_col_merge(int32_t n2, int32_t nspli
   if (ctl->done) return;
   const double *a = cur ? bufA1 : bufA0;
   double *an = cur ? bufA0 : bufA1;
-  const int j = blockIdx.x * 256 + threadIdx.x;
+  const int c = threadIdx.x & 63, g = threadIdx.x >> 6;
+  const int j = blockIdx.x * 64 + c;
+  double M = -INFINITY, S = 0.0;
+  if (j < n2)
+    for (int q = g; q < nsplit; q += 4)
+      lse2_merge(M, S, pm[static_cast<int64_t>(q) * n2 + j], ps[static_cast<int64_t>(q) * n2 + j]);
+  __shared__ double fm[4][64], fs[4][64];
+  fm[g][c] = M;
+  fs[g][c] = S;
+  __syncthreads();
   double e = 0.0;
-  if (j < n2) {
-    double M = -INFINITY, S = 0.0;
-    for (int q = 0; q < nsplit; ++q) M = fmax(M, pm[static_cast<int64_t>(q) * n2 + j]);
-    if (M > -INFINITY)
-      for (int q = 0; q < nsplit; ++q) {
-        const double mq = pm[static_cast<int64_t>(q) * n2 + j];
-        if (mq > -INFINITY) S += ps[static_cast<int64_t>(q) * n2 + j] * static_cast<double>(exp2f(static_cast<float>(mq - M)));
-      }
+  if (g == 0 && j < n2) {
+    for (int q = 1; q < 4; ++q) lse2_merge(M, S, fm[q][c], fs[q][c]);
     const double l2 = M + log2(S);  // log2 of the column sum
     an[j] = a[j] + eps * (log_nu - l2 * kLn2);
     e = fabs(exp2(l2) - nu);
