@@ -295,6 +295,17 @@ int fa_adam_step(float *params, const float *grad, float *m, float *v, int32_t c
                  double lr, double beta1, double beta2, double eps_adam, int32_t step,
                  void *stream);
 
+/* ---------------------------------------------------------------- measurement */
+
+/* Achievable read rate of the device (a reference for the streaming passes, not
+ * part of Algorithm 1): reads x[0..n) once with 16-byte non-temporal loads and
+ * writes one partial sum per thread.
+ *   x        device float[n], n a multiple of 4, 16-byte aligned (in)
+ *   partial  device float[nblocks * 256] (out, overwritten)
+ *   nblocks  workgroups of 256 threads, 1..65536
+ * Time it with events on `stream`; bytes read = 4 n.  Errors: FA_ERR_ARG. */
+int fa_stream_read(const float *x, size_t n, float *partial, int32_t nblocks, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -291,3 +291,8 @@ def mlp_backward(prm: torch.Tensor, x: torch.Tensor, t: torch.Tensor, act: torch
 def adam_step(prm, grad, m, v, step: int, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
     _lib().call("fa_adam_step", _ptr(prm), _ptr(grad), _ptr(m), _ptr(v), prm.numel(), float(lr), float(beta1),
                 float(beta2), float(eps), int(step), _stream())
+
+
+def stream_read(x, partial, nblocks: int):
+    """One streaming read of x (float32, numel a multiple of 4) on the current stream."""
+    _lib().call("fa_stream_read", _ptr(x), x.numel(), _ptr(partial), int(nblocks), _stream())

@@ -23,7 +23,7 @@ EXPORTS = [
     "fa_propagate", "fa_cost", "fa_sinkhorn_workspace_size", "fa_sinkhorn", "fa_plan",
     "fa_align_workspace_size", "fa_align", "fa_node_feature_dim", "fa_node_features_workspace_size",
     "fa_node_features", "fa_mlp_param_count", "fa_mlp_act_floats", "fa_mlp_forward",
-    "fa_mlp_backward", "fa_adam_step",
+    "fa_mlp_backward", "fa_adam_step", "fa_stream_read",
 ]
 
 
@@ -87,6 +87,7 @@ _SIGS = {
     "fa_mlp_forward": (C.c_int, [_P, _P, _I32, _P, _P, _P]),
     "fa_mlp_backward": (C.c_int, [_P, _P, _P, _I32, _P, _P, _P, _P]),
     "fa_adam_step": (C.c_int, [_P, _P, _P, _P, _I32, _D, _D, _D, _D, _I32, _P]),
+    "fa_stream_read": (C.c_int, [_P, _SZ, _P, _I32, _P]),
 }
 
 

@@ -5,8 +5,10 @@
 // v_mfma_f32_32x32x16_bf16, FP32 accumulation either way.  One workgroup owns a
 // 128x128 output tile (four waves, 64x64 each as 2x2 blocks of 32x32), runs both
 // K loops into two accumulator sets and applies the exponential mix once, so
-// C_node is written a single time.  Workgroup ids are remapped so tiles that
-// share operand panels run on the same XCD (its own L2).
+// C_node is written a single time.  Operands move in 16-byte pieces: 128 bytes of
+// K per row and step, staged through padded LDS rows, with the next step's
+// global loads in flight during the current step's MFMAs.  Workgroup ids are
+// remapped so tiles that share operand panels run on the same XCD (its own L2).
 #include "fa_common.h"
 #include "fa_internal.h"
 
@@ -15,109 +17,130 @@ namespace fa {
 typedef float floatx16 __attribute__((ext_vector_type(16)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
-template <typename T>
-struct GemmTraits;
-template <>
-struct GemmTraits<float> {
-  static constexpr int KC = 16;    // K elements per LDS stage
-  static constexpr int KSTEP = 2;  // K per MFMA
-  static constexpr int WPR = 16;   // 32-bit words per tile row (KC * 4 / 4)
-};
-template <>
-struct GemmTraits<uint16_t> {
-  static constexpr int KC = 32;
-  static constexpr int KSTEP = 16;
-  static constexpr int WPR = 16;   // KC * 2 / 4
+constexpr int kTile = 128;              // output tile per workgroup (4 waves, 64 x 64 each)
+constexpr int kChunkBytes = 128;        // K bytes of each operand row staged per step
+constexpr int kLdsRow = kChunkBytes + 16;  // padded LDS row: 16-byte fragment reads stay conflict-free
+
+// One step's operand tile (kTile rows x kChunkBytes) held in registers while the
+// previous step computes: 1024 16-byte pieces, four per thread.
+struct Stage {
+  uint4 v[4];
 };
 
-constexpr int kTile = 128;
-constexpr int kLdsStride = 17;  // words per LDS row: 16 + 1 pad (odd stride, no bank conflicts)
-
-// Stage a 128 x KC tile of a row-major [rows x K] operand into LDS as 32-bit words.
+// Load rows [row0, row0+128) x K elements [k0, k0 + kChunkBytes/sizeof(T)) of a
+// row-major [rows x K] operand.  vec: every row starts 16-byte aligned and K is a
+// whole number of 16-byte pieces, so pieces are single vector loads; otherwise the
+// pieces are assembled element by element.  Out-of-range rows and K are zero.
 template <typename T>
-__device__ inline void stage_tile(const T *__restrict__ M, int32_t rows, int32_t K, int row0, int k0,
-                                  uint32_t *__restrict__ lds) {
-  constexpr int EPW = 4 / sizeof(T);  // elements per word
-  constexpr int WPR = GemmTraits<T>::WPR;
-  for (int wd = threadIdx.x; wd < kTile * WPR; wd += 256) {
-    const int r = wd / WPR, c = wd % WPR;
-    const int grow = row0 + r;
-    const int gk = k0 + c * EPW;
-    uint32_t v = 0;
-    if (grow < rows) {
+__device__ inline void load_stage(const T *__restrict__ M, int32_t rows, int32_t K, int row0, int k0, bool vec,
+                                  Stage &st) {
+  constexpr int EPP = 16 / sizeof(T);  // elements per piece
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int q = threadIdx.x + 256 * i;
+    const int r = q >> 3, piece = q & 7;
+    const int grow = row0 + r, gk = k0 + piece * EPP;
+    uint4 v = make_uint4(0u, 0u, 0u, 0u);
+    if (grow < rows && gk < K) {
       const T *p = M + static_cast<int64_t>(grow) * K + gk;
-      if (EPW == 1) {
-        if (gk < K) v = reinterpret_cast<const uint32_t *>(p)[0];
+      if (vec) {
+        v = *reinterpret_cast<const uint4 *>(p);
       } else {
-        const uint16_t *h = reinterpret_cast<const uint16_t *>(p);
-        const uint32_t lo = gk < K ? h[0] : 0u;
-        const uint32_t hi = gk + 1 < K ? h[1] : 0u;
-        v = lo | (hi << 16);
+        T e[EPP];
+#pragma unroll
+        for (int t = 0; t < EPP; ++t) e[t] = gk + t < K ? p[t] : T(0);
+        __builtin_memcpy(&v, e, 16);
       }
     }
-    lds[r * kLdsStride + c] = v;
+    st.v[i] = v;
   }
 }
 
+__device__ inline void store_stage(const Stage &st, uint8_t *__restrict__ lds) {
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int q = threadIdx.x + 256 * i;
+    *reinterpret_cast<uint4 *>(lds + (q >> 3) * kLdsRow + (q & 7) * 16) = st.v[i];
+  }
+}
+
+// The MFMA steps of one staged chunk for a wave's 64 x 64 block (2 x 2 blocks of 32 x 32).
 template <typename T>
-__device__ inline void mma_step(const uint32_t *__restrict__ la, const uint32_t *__restrict__ lb, int ks,
-                                int wm, int wn, int lane, floatx16 (&acc)[2][2]);
+__device__ inline void mma_chunk(const uint8_t *__restrict__ la, const uint8_t *__restrict__ lb, int wm, int wn,
+                                 int lane, floatx16 (&acc)[2][2]);
 
+// FP32, v_mfma_f32_32x32x2_f32: in each step lane l supplies A[m = l%32][k] and
+// B[k][n = l%32] for one k of a pair.  The sum over K is order-free, so each
+// 8-element group of K is split as lanes 0-31 -> k0..k0+3, lanes 32-63 -> k0+4..k0+7
+// (one 16-byte LDS read per fragment) and step t pairs k0+t with k0+4+t.
 template <>
-__device__ inline void mma_step<float>(const uint32_t *__restrict__ la, const uint32_t *__restrict__ lb, int ks,
-                                       int wm, int wn, int lane, floatx16 (&acc)[2][2]) {
-  // 32x32x2: lane holds A[m = lane%32][k = lane/32] and B[k = lane/32][n = lane%32].
-  const int k = ks * 2 + (lane >> 5);
-  float av[2], bv[2];
+__device__ inline void mma_chunk<float>(const uint8_t *__restrict__ la, const uint8_t *__restrict__ lb, int wm,
+                                        int wn, int lane, floatx16 (&acc)[2][2]) {
+  const int half = lane >> 5, r = lane & 31;
 #pragma unroll
-  for (int q = 0; q < 2; ++q) {
-    av[q] = __uint_as_float(la[(wm * 64 + q * 32 + (lane & 31)) * kLdsStride + k]);
-    bv[q] = __uint_as_float(lb[(wn * 64 + q * 32 + (lane & 31)) * kLdsStride + k]);
-  }
+  for (int g = 0; g < kChunkBytes / 32; ++g) {
+    float4 av[2], bv[2];
 #pragma unroll
-  for (int p = 0; p < 2; ++p)
-#pragma unroll
-    for (int q = 0; q < 2; ++q) acc[p][q] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[p], bv[q], acc[p][q], 0, 0, 0);
-}
-
-template <>
-__device__ inline void mma_step<uint16_t>(const uint32_t *__restrict__ la, const uint32_t *__restrict__ lb, int ks,
-                                          int wm, int wn, int lane, floatx16 (&acc)[2][2]) {
-  // 32x32x16: lane holds A[m = lane%32][k = 8*(lane/32) .. +8] (4 words), same for B.
-  const int w0 = ks * 8 + (lane >> 5) * 4;
-  bf16x8 av[2], bv[2];
-#pragma unroll
-  for (int q = 0; q < 2; ++q) {
-    uint32_t wa[4], wb[4];
-    const uint32_t *pa = la + (wm * 64 + q * 32 + (lane & 31)) * kLdsStride + w0;
-    const uint32_t *pb = lb + (wn * 64 + q * 32 + (lane & 31)) * kLdsStride + w0;
+    for (int q = 0; q < 2; ++q) {
+      av[q] = *reinterpret_cast<const float4 *>(la + (wm * 64 + q * 32 + r) * kLdsRow + g * 32 + half * 16);
+      bv[q] = *reinterpret_cast<const float4 *>(lb + (wn * 64 + q * 32 + r) * kLdsRow + g * 32 + half * 16);
+    }
+    const float *a0 = reinterpret_cast<const float *>(&av[0]), *a1 = reinterpret_cast<const float *>(&av[1]);
+    const float *b0 = reinterpret_cast<const float *>(&bv[0]), *b1 = reinterpret_cast<const float *>(&bv[1]);
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
-      wa[t] = pa[t];
-      wb[t] = pb[t];
+      acc[0][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(a0[t], b0[t], acc[0][0], 0, 0, 0);
+      acc[0][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(a0[t], b1[t], acc[0][1], 0, 0, 0);
+      acc[1][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(a1[t], b0[t], acc[1][0], 0, 0, 0);
+      acc[1][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(a1[t], b1[t], acc[1][1], 0, 0, 0);
     }
-    __builtin_memcpy(&av[q], wa, 16);
-    __builtin_memcpy(&bv[q], wb, 16);
   }
-#pragma unroll
-  for (int p = 0; p < 2; ++p)
-#pragma unroll
-    for (int q = 0; q < 2; ++q) acc[p][q] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[p], bv[q], acc[p][q], 0, 0, 0);
 }
 
+// BF16, v_mfma_f32_32x32x16_bf16: lane l supplies A[m = l%32][k = 8(l/32) .. +8] and
+// the same slice of B, one 16-byte LDS read each.
+template <>
+__device__ inline void mma_chunk<uint16_t>(const uint8_t *__restrict__ la, const uint8_t *__restrict__ lb, int wm,
+                                           int wn, int lane, floatx16 (&acc)[2][2]) {
+  const int half = lane >> 5, r = lane & 31;
+#pragma unroll
+  for (int ks = 0; ks < kChunkBytes / 32; ++ks) {
+    bf16x8 av[2], bv[2];
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      av[q] = *reinterpret_cast<const bf16x8 *>(la + (wm * 64 + q * 32 + r) * kLdsRow + ks * 32 + half * 16);
+      bv[q] = *reinterpret_cast<const bf16x8 *>(lb + (wn * 64 + q * 32 + r) * kLdsRow + ks * 32 + half * 16);
+    }
+#pragma unroll
+    for (int p = 0; p < 2; ++p)
+#pragma unroll
+      for (int q = 0; q < 2; ++q) acc[p][q] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[p], bv[q], acc[p][q], 0, 0, 0);
+  }
+}
+
+// acc += A[m0.., :] B[n0.., :]^T over all of K.  The next chunk's global loads are
+// issued before the current chunk's MFMAs, so they are in flight during the math.
 template <typename T>
 __device__ inline void gemm_nt(const T *__restrict__ A, const T *__restrict__ B, int32_t n1, int32_t n2, int32_t K,
-                               int m0, int n0, uint32_t *la, uint32_t *lb, floatx16 (&acc)[2][2]) {
-  constexpr int KC = GemmTraits<T>::KC, KSTEP = GemmTraits<T>::KSTEP;
+                               int m0, int n0, uint8_t *la, uint8_t *lb, floatx16 (&acc)[2][2]) {
+  constexpr int KE = kChunkBytes / sizeof(T);
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int wm = wv >> 1, wn = wv & 1;
-  for (int k0 = 0; k0 < K; k0 += KC) {
+  const bool vec = (static_cast<int64_t>(K) * sizeof(T)) % 16 == 0 &&
+                   (reinterpret_cast<uintptr_t>(A) & 15) == 0 && (reinterpret_cast<uintptr_t>(B) & 15) == 0;
+  Stage sa, sb;
+  load_stage<T>(A, n1, K, m0, 0, vec, sa);
+  load_stage<T>(B, n2, K, n0, 0, vec, sb);
+  for (int k0 = 0; k0 < K; k0 += KE) {
+    __syncthreads();  // the previous chunk's LDS reads are done
+    store_stage(sa, la);
+    store_stage(sb, lb);
     __syncthreads();
-    stage_tile<T>(A, n1, K, m0, k0, la);
-    stage_tile<T>(B, n2, K, n0, k0, lb);
-    __syncthreads();
-#pragma unroll
-    for (int ks = 0; ks < KC / KSTEP; ++ks) mma_step<T>(la, lb, ks, wm, wn, lane, acc);
+    if (k0 + KE < K) {
+      load_stage<T>(A, n1, K, m0, k0 + KE, vec, sa);
+      load_stage<T>(B, n2, K, n0, k0 + KE, vec, sb);
+    }
+    mma_chunk<T>(la, lb, wm, wn, lane, acc);
   }
 }
 
@@ -125,8 +148,8 @@ template <typename TX, typename TR>
 __global__ __launch_bounds__(256) void k_featsim(const TX *__restrict__ X1, const TX *__restrict__ X2, int32_t d,
                                                  const TR *__restrict__ R1, const TR *__restrict__ R2, int32_t nL,
                                                  int32_t n1, int32_t n2, float alpha, float *__restrict__ C) {
-  __shared__ uint32_t la[kTile * kLdsStride];
-  __shared__ uint32_t lb[kTile * kLdsStride];
+  __shared__ __align__(16) uint8_t la[kTile * kLdsRow];
+  __shared__ __align__(16) uint8_t lb[kTile * kLdsRow];
   const int ntm = (n1 + kTile - 1) / kTile, ntn = (n2 + kTile - 1) / kTile;
   const int nb = ntm * ntn;
   // XCD-aware id: consecutive ids land on different XCDs; give each XCD a

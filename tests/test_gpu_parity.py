@@ -105,8 +105,11 @@ def test_sddmm_intra_costs(api, case):
     assert np.allclose(w2, C2.data, rtol=1e-5, atol=1e-9)
 
 
-@pytest.mark.parametrize("shape", [(300, 270, 40, 37), (129, 257, 0, 5), (64, 64, 32, 0), (1, 130, 3, 2)])
+@pytest.mark.parametrize("shape", [(300, 270, 40, 37), (129, 257, 0, 5), (64, 64, 32, 0), (1, 130, 3, 2),
+                                   (300, 270, 40, 200), (257, 390, 96, 0)])
 def test_feature_sim_fp32(api, shape):
+    """Tiles of 128 with ragged edges; K below, at and across several 32-element
+    steps, with 16-byte vector staging (K*4 a multiple of 16) and element staging."""
     n1, n2, d, nL = shape
     r = np.random.default_rng(n1 + n2)
     X1, X2 = r.standard_normal((n1, d)), r.standard_normal((n2, d))
@@ -119,8 +122,10 @@ def test_feature_sim_fp32(api, shape):
     assert np.allclose(got, want, rtol=2e-6, atol=2e-6)
 
 
-def test_feature_sim_bf16(api):
-    n1, n2, d, nL = 300, 260, 64, 45
+@pytest.mark.parametrize("shape", [(300, 260, 64, 45), (257, 300, 136, 72), (130, 129, 7, 200)])
+def test_feature_sim_bf16(api, shape):
+    """K across several 64-element steps, vector (K*2 a multiple of 16) and element staging."""
+    n1, n2, d, nL = shape
     r = np.random.default_rng(5)
     X1, X2 = r.standard_normal((n1, d)), r.standard_normal((n2, d))
     R1, R2 = r.random((n1, nL)) * 0.3, r.random((n2, nL)) * 0.3
