@@ -8,8 +8,8 @@ attributes, 2% anchors, eps = 0.02, 30 outer iterations, inner Sinkhorn capped a
 
 The headline form stores the plan in BF16 (FP32 cost and SpMM intermediates,
 FP64 duals) and starts the first inner solve from the learned warm start when
-trained weights are present; the plain form (FP32 plan, cold starts) is timed
-once beside it.  Inputs are resident in HBM before the timed region.
+trained weights are present (later solves start from zero duals unless --carry);
+the plain form (FP32 plan, cold starts) is timed once beside it.  Inputs are resident in HBM before the timed region.
 
 Prints one JSON line.  ``--gpus N`` with N > 1 exits: this build runs on one GPU.
 """
@@ -45,6 +45,8 @@ def parse():
     ap.add_argument("--no-plain", action="store_true", help="skip the plain FP32 comparison run")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cold", action="store_true", help="headline form without the learned warm start")
+    ap.add_argument("--carry", action="store_true",
+                    help="headline form starts every later solve from the previous solve's duals")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one 4 GiB device-to-device copy first (reference for HBM byte counters)")
     return ap.parse_args()
@@ -141,7 +143,8 @@ def main():
     if not args.cold:
         mlp = warm.load_weights(dev)
     common = dict(eps=cfg.eps, outer_iters=T, inner_iters=cfg.inner_iters, tol=1e-6, check_every=1, profile=1)
-    p_head = api.params(plan_dtype="bf16", feat_dtype="bf16", warm_start=mlp is not None, **common)
+    p_head = api.params(plan_dtype="bf16", feat_dtype="bf16", warm_start=mlp is not None,
+                        carry_duals=args.carry, **common)
     p_plain = api.params(plan_dtype="f32", feat_dtype="f32", warm_start=False, **common)
 
     # runtime warm-up on a tiny pair (loads the code objects; not a benchmark step)
@@ -170,6 +173,7 @@ def main():
         sb = 2 if p.plan_dtype == binding.FA_BF16 else 4
         out = dict(align_s=ms / 1e3, outer_iters_per_s=T / (ms / 1e3), inner_total=int(st.inner_total),
                    marg_err_last=float(st.marg_err), converged_all=bool(st.converged_all),
+                   inner_err=[float(x) for x in list(st.inner_err)[:min(T, 64)]],
                    phase_ms=dict(phase1=st.phase_ms[0], cost=st.phase_ms[1], sinkhorn=st.phase_ms[2],
                                  plan=st.phase_ms[3]),
                    kernels={})
@@ -246,7 +250,7 @@ def main():
                                      f"noise={cfg.noise:g} d={pair.X1.shape[1]} anchors={len(pair.anchors)} "
                                      f"eps={cfg.eps:g} outer={T} inner<={cfg.inner_iters} tol=1e-6",
                             n1=pair.n1, n2=pair.n2, outer_iters=T, inner_cap=cfg.inner_iters, tol=1e-6),
-                warm_start=mlp is not None, headline=head, plain_fp32=plain, argmax_agreement=agree,
+                warm_start=mlp is not None, carry_duals=args.carry, headline=head, plain_fp32=plain, argmax_agreement=agree,
                 spmm_gbps=spmm, roofline=roofline, cpu_baseline=cpu)
     print(json.dumps(line), flush=True)
 

@@ -82,6 +82,9 @@ typedef struct {
   int32_t warm_start; /* 0: cold duals; 1: learned row duals for the first solve */
   int32_t chunk_rows; /* rows per Phase-2 chunk (0: automatic) */
   int32_t profile;    /* 1: time every launch with HIP events (fa_stats.kernel_ms) */
+  int32_t carry_duals;/* 0: every inner solve starts from a = b = 0; 1: solves after the first
+                         start from the previous solve's final duals.  The fixed point of each
+                         solve is the same; only the iterates before convergence differ. */
 } fa_params;
 
 /* Run statistics returned by fa_align (host struct). */

@@ -37,6 +37,11 @@ with their reasons in the design notes of the repository):
 * R11 CSR: undirected, symmetrised, self-loops dropped, duplicates merged,
       columns sorted; isolated nodes have an all-zero normalised row.
 * R12 argmax ties resolve to the lowest column index.
+* R14 (variant) With carry_duals, every inner solve after the first starts from
+      the final duals of the previous one instead of zeros.  A solve run to
+      convergence reaches the same optimum from any start (its duals are unique up
+      to a constant shift that the plan and the cost update do not see), so the
+      variant changes only iterates that stop before convergence.
 """
 from __future__ import annotations
 
@@ -71,6 +76,7 @@ class Params:
     outer_iters: int = 10
     inner_iters: int = 50
     feat_l2norm: bool = True
+    carry_duals: bool = False            # R14 variant: later solves start from the previous duals
 
     @property
     def lp(self) -> float:
@@ -301,8 +307,11 @@ def align(n1, rowptr1, colidx1, n2, rowptr2, colidx2, X1, X2, anchors, p: Params
     for t in range(p.outer_iters):
         C = cost_update(ph["C_node"], ph["C_anc"], ph["C1"], ph["C2"], ph["Abar1"],
                         ph["Abar2"], S, logS, p)
-        b0 = b_init if (t == 0 and b_init is not None) else None
-        a, b, it, err = sinkhorn(C, p.eps, p.inner_iters, p.tol, None, b0)
+        if t > 0 and p.carry_duals:
+            a0, b0 = a, b
+        else:
+            a0, b0 = None, (b_init if (t == 0 and b_init is not None) else None)
+        a, b, it, err = sinkhorn(C, p.eps, p.inner_iters, p.tol, a0, b0)
         logS = (a[None, :] + b[:, None] - C) / p.eps
         S = np.exp(logS)
         iters.append(it)

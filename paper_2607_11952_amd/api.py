@@ -88,7 +88,7 @@ def params(**kw) -> B.fa_params:
     for k, v in kw.items():
         if k in ("plan_dtype", "feat_dtype") and isinstance(v, str):
             v = {"f32": B.FA_F32, "bf16": B.FA_BF16}[v]
-        if k in ("feat_l2norm", "warm_start", "profile"):
+        if k in ("feat_l2norm", "warm_start", "profile", "carry_duals"):
             v = int(v)
         setattr(p, k, v)
     if "lambda_p" not in kw:

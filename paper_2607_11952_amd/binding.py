@@ -40,6 +40,7 @@ class fa_params(C.Structure):
         ("check_every", C.c_int32), ("plan_dtype", C.c_int32), ("feat_dtype", C.c_int32),
         ("feat_l2norm", C.c_int32), ("warm_start", C.c_int32), ("chunk_rows", C.c_int32),
         ("profile", C.c_int32),
+        ("carry_duals", C.c_int32),
     ]
 
 

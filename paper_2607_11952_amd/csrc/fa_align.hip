@@ -248,10 +248,10 @@ extern "C" int fa_align(const fa_csr *A1, const fa_csr *A2, const float *X1, con
     if (p->warm_start && t == 0) {
       FA_TRY(warm_start_duals(mlp_weights, B.feat, n1, B.act, p->eps, B.bad + 2, b_out, s));
       FA_TRY(launch_fill_f64(a_out, n2, 0.0, s));
-    } else {
+    } else if (t == 0 || !p->carry_duals) {
       FA_TRY(launch_fill_f64(a_out, n2, 0.0, s));
       FA_TRY(launch_fill_f64(b_out, n1, 0.0, s));
-    }
+    }  // else: the previous solve's duals are the start
     int32_t *it_slot = B.st_iters + (t < 64 ? t : 63);
     double *er_slot = B.st_err + (t < 64 ? t : 63);
     FA_TRY(run_sinkhorn(B.C, n1, n2, p->eps, a_out, b_out, p->inner_iters, p->tol, p->check_every, it_slot, er_slot,

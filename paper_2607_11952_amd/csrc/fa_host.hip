@@ -47,6 +47,7 @@ extern "C" void fa_default_params(fa_params *p) {
   p->warm_start = 0;
   p->chunk_rows = 0;
   p->profile = 0;
+  p->carry_duals = 0;
 }
 
 extern "C" int fa_device_check(void) {

@@ -334,6 +334,28 @@ def test_outer_loop_fixed_cost_equals_sinkhorn_at_eps_over_t():
     assert np.allclose(out["S"], O.plan(C0, a, b, p.eps / T), atol=1e-11)
 
 
+def test_carry_over_start_reaches_the_same_plans():
+    """Each inner solve has one optimum whatever its start (up to a constant shift
+    of the duals that neither the plan nor the cost update sees): run to convergence,
+    starts carried over from the previous solve and zero starts give the same plan
+    at every outer iteration, and the carried start needs fewer iterations."""
+    import dataclasses
+    n = 14
+    e1, e2, X1, X2, L, pi = _small_pair(n=n, seed=34, anchors=2, noise=0.3)
+    # lambda_n = 0 keeps the kernel's dynamic range small enough for every solve to
+    # converge to 1e-13 (-log(delta) entries slow Sinkhorn down by orders of magnitude)
+    p0 = O.Params(eps=0.3, lambda_n=0.0, outer_iters=3, inner_iters=20000, tol=1e-13, k_r=3)
+    zero = _run(n, e1, n, e2, X1, X2, L, p0, keep_history=True)
+    carry = _run(n, e1, n, e2, X1, X2, L, dataclasses.replace(p0, carry_duals=True), keep_history=True)
+    for hz, hc in zip(zero["history"], carry["history"]):
+        Sz = O.plan(hz["C"], hz["a"], hz["b"], p0.eps)
+        Sc = O.plan(hc["C"], hc["a"], hc["b"], p0.eps)
+        assert np.allclose(Sz, Sc, rtol=1e-8, atol=1e-13)
+    assert max(zero["errs"] + carry["errs"]) <= 1e-13
+    assert carry["iters"][0] == zero["iters"][0]
+    assert sum(carry["iters"][1:]) < sum(zero["iters"][1:])
+
+
 def test_permutation_equivariance():
     n = 30
     e1, e2, X1, X2, L, pi = _small_pair(n=n, seed=33, anchors=3)
