@@ -38,9 +38,10 @@ static SinkLayout sink_layout(int32_t n1, int32_t n2) {
   SinkLayout L;
   L.V = (n2 % 4 == 0) ? 4 : 1;
   L.ncolblk = ceil_div(n2, 256 * L.V);
-  // about 8192 workgroups (four to five rounds of resident ones): long enough row
-  // ranges per workgroup to keep the streams sequential, short enough tail
-  int want = ceil_div(8192, L.ncolblk > 0 ? L.ncolblk : 1);
+  // about 5000 workgroups (three rounds of resident ones): long row ranges keep
+  // each workgroup's stream sequential (measured: ~45 splits of 2,700 rows at
+  // n = 120k beat 70, 105 or 139 splits), while the tail stays short
+  int want = ceil_div(5120, L.ncolblk > 0 ? L.ncolblk : 1);
   int maxs = n1 / 64 > 1 ? n1 / 64 : 1;  // at least 64 rows per split: partials stay small next to C
   L.nsplit = want < 1 ? 1 : (want > maxs ? maxs : want);
   L.rows_per_split = ceil_div(n1 > 0 ? n1 : 1, L.nsplit);

@@ -57,8 +57,10 @@ struct VLoad<uint16_t, 2> {
 __device__ inline int bcast_i(int v, int u) { return __builtin_amdgcn_readlane(v, u); }
 __device__ inline float bcast_f(float v, int u) { return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), u)); }
 
-// Gathers kept in flight per wave in stage 1 (eight row segments of S).
+// Gathers kept in flight per wave: stage 1 (row segments of S), stage 2 (Zt
+// column segments, per value set).  Both divide the 64-entry neighbour chunks.
 constexpr int kUnroll1 = 8;
+constexpr int kUnroll2 = 8;
 
 // Stage 1 (left SpMM into the block-transposed layout).
 //   grid.x = row block within the chunk, grid.y = column tile of 64*VW columns;
@@ -102,8 +104,10 @@ __global__ __launch_bounds__(64 * 64 / RW) void k_stage1(const int64_t *__restri
           my_a = wa ? wa[base + lane] : 1.f;
           if (TWO) my_b = csb[my_k];
         }
-        int u = 0;
-        for (; u + kUnroll1 <= cnt; u += kUnroll1) {
+        // Whole groups of kUnroll1 even past cnt: lanes >= cnt hold index 0 and zero
+        // weights, so the extra gathers re-read one hot row and add nothing, and a
+        // row of degree d costs ceil(d / kUnroll1) round trips instead of a serial tail.
+        for (int u = 0; u < cnt; u += kUnroll1) {
           float sv[kUnroll1][VW];
 #pragma unroll
           for (int q = 0; q < kUnroll1; ++q) {
@@ -119,18 +123,6 @@ __global__ __launch_bounds__(64 * 64 / RW) void k_stage1(const int64_t *__restri
               a[v] += fa * sv[q][v];
               if (TWO) b[v] += fb * sv[q][v];
             }
-          }
-        }
-        for (; u < cnt; ++u) {
-          const int k = bcast_i(my_k, u);
-          float sv[VW];
-          VLoad<TS, VW>::run(Sc + static_cast<int64_t>(k) * n2, sv);
-          const float fa = bcast_f(my_a, u);
-          const float fb = TWO ? bcast_f(my_b, u) : 0.f;
-#pragma unroll
-          for (int v = 0; v < VW; ++v) {
-            a[v] += fa * sv[v];
-            if (TWO) b[v] += fb * sv[v];
           }
         }
       }
@@ -155,10 +147,11 @@ __global__ __launch_bounds__(64 * 64 / RW) void k_stage1(const int64_t *__restri
   constexpr int LS = kZtRows + 4;                   // padded column stride keeps float4 alignment
   __shared__ float lds[NL * LS];
   const int ct = blockIdx.y * (64 * VW);
+  constexpr int NSET = TWO ? 2 : 1;  // the value sets of a column are interleaved: [block][l][set][r]
   const int64_t base = static_cast<int64_t>(blk) * n2;
 #pragma unroll
   for (int set = 0; set < (TWO ? 2 : 1); ++set) {
-    float *Z = set ? Zb : Za;
+    (void)Zb;
 #pragma unroll
     for (int turn = 0; turn < 64 / LP; ++turn) {
       __syncthreads();
@@ -175,7 +168,7 @@ __global__ __launch_bounds__(64 * 64 / RW) void k_stage1(const int64_t *__restri
         const int cl = q / (kZtRows / 4), part = q % (kZtRows / 4);
         if (c0 + cl < n2) {
           const float4 val = *reinterpret_cast<const float4 *>(&lds[cl * LS + part * 4]);
-          *reinterpret_cast<float4 *>(Z + (base + c0 + cl) * kZtRows + part * 4) = val;
+          *reinterpret_cast<float4 *>(Za + ((base + c0 + cl) * NSET + set) * kZtRows + part * 4) = val;
         }
       }
     }
@@ -219,8 +212,10 @@ __global__ __launch_bounds__(512) void k_stage2(const int64_t *__restrict__ rowp
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int j0 = blockIdx.x * 64;
   const int blk = blockIdx.y;
-  const float *za = Za + static_cast<int64_t>(blk) * n2 * kZtRows + lane;
-  const float *zb = COST ? Zb + static_cast<int64_t>(blk) * n2 * kZtRows + lane : nullptr;
+  // both value sets of column l of the block sit next to each other (512 bytes)
+  constexpr int NSET = COST ? 2 : 1;
+  (void)Zb;
+  const float *za = Za + static_cast<int64_t>(blk) * n2 * (kZtRows * NSET) + lane;
   for (int jj = 0; jj < 8; ++jj) {
     const int j = j0 + w * 8 + jj;
     double E = 0.0, P = 0.0;
@@ -232,38 +227,23 @@ __global__ __launch_bounds__(512) void k_stage2(const int64_t *__restrict__ rowp
         float my_w = 0.f, my_c = 0.f;
         if (lane < cnt) {
           my_l = col[base + lane];
-          if (COST) {
-            my_w = w2a[base + lane];
-            my_c = cs2b[my_l];
-          }
+          my_w = COST ? w2a[base + lane] : 1.f;
+          if (COST) my_c = cs2b[my_l];
         }
-        int u = 0;
-        for (; u + 4 <= cnt; u += 4) {
-          float x[4], y[4];
+        // Whole groups of kUnroll2 (lanes >= cnt hold column 0 and zero weights):
+        // 2 kUnroll2 gathers in flight per wave and no serial tail.
+        for (int u = 0; u < cnt; u += kUnroll2) {
+          float x[kUnroll2], y[kUnroll2];
 #pragma unroll
-          for (int t = 0; t < 4; ++t) {
+          for (int t = 0; t < kUnroll2; ++t) {
             const int64_t l = bcast_i(my_l, u + t);
-            x[t] = za[l * kZtRows];
-            if (COST) y[t] = zb[l * kZtRows];
+            x[t] = za[l * (kZtRows * NSET)];
+            if (COST) y[t] = za[l * (kZtRows * NSET) + kZtRows];
           }
 #pragma unroll
-          for (int t = 0; t < 4; ++t) {
-            if (COST) {
-              E = fma(static_cast<double>(bcast_f(my_w, u + t)), static_cast<double>(x[t]), E);
-              P = fma(static_cast<double>(bcast_f(my_c, u + t)), static_cast<double>(y[t]), P);
-            } else {
-              E += static_cast<double>(x[t]);
-            }
-          }
-        }
-        for (; u < cnt; ++u) {
-          const int64_t l = bcast_i(my_l, u);
-          const float x = za[l * kZtRows];
-          if (COST) {
-            E = fma(static_cast<double>(bcast_f(my_w, u)), static_cast<double>(x), E);
-            P = fma(static_cast<double>(bcast_f(my_c, u)), static_cast<double>(zb[l * kZtRows]), P);
-          } else {
-            E += static_cast<double>(x);
+          for (int t = 0; t < kUnroll2; ++t) {
+            E = fma(static_cast<double>(bcast_f(my_w, u + t)), static_cast<double>(x[t]), E);
+            if (COST) P = fma(static_cast<double>(bcast_f(my_c, u + t)), static_cast<double>(y[t]), P);
           }
         }
       }
