@@ -55,6 +55,7 @@ __all__ = [
     "Params", "build_csr", "row_normalized", "onehot_anchors", "positional_encoding",
     "l2_normalize_rows", "feature_similarity", "propagate", "anchor_cost", "intra_costs",
     "cost_update", "lse", "sinkhorn", "plan", "marginal_error", "align",
+    "similarity_entry", "propagate_entry", "intra_row_entries", "cost_entry", "row_dual_entry", "plan_entry",
 ]
 
 
@@ -321,3 +322,55 @@ def align(n1, rowptr1, colidx1, n2, rowptr2, colidx2, X1, X2, anchors, p: Params
     argmax = np.argmax(S, axis=1) if n2 > 0 else np.zeros(n1, dtype=np.int64)
     return dict(S=S, a=a, b=b, argmax=argmax, C=C, iters=iters, errs=errs,
                 phase1=ph, history=hist)
+
+
+# ----------------------------------------------------------------------------
+# Single entries, for sampled checks at sizes where the dense matrices above do
+# not fit in host memory.  Each is the definition above evaluated at one (i, j)
+# from the few operand entries it depends on.
+# ----------------------------------------------------------------------------
+
+def similarity_entry(x1, x2, r1, r2, alpha: float) -> float:
+    """C_node[i, j] (Phase 1) from row i of X1, R1 and row j of X2, R2 (already normalised)."""
+    x1, x2, r1, r2 = (np.asarray(v, dtype=np.float64) for v in (x1, x2, r1, r2))
+    return float(alpha * np.exp(-(r1 @ r2)) + (1.0 - alpha) * np.exp(-(x1 @ x2)))
+
+
+def propagate_entry(C_block, deg1_i: int, deg2_j: int) -> float:
+    """(Abar1 C Abar2^T)[i, j] with C_block = C[N1(i)][:, N2(j)]; every entry of row i
+    of Abar1 is 1/deg1(i) and of row j of Abar2 is 1/deg2(j)."""
+    if deg1_i == 0 or deg2_j == 0:
+        return 0.0
+    return float(np.asarray(C_block, dtype=np.float64).sum() / (float(deg1_i) * float(deg2_j)))
+
+
+def intra_row_entries(r_i, R_nbrs, scale) -> np.ndarray:
+    """Entries of C1 (or C2) on one row's support: (R R^T)[i, k] * scale, scale being the
+    Abar factor (1/deg1(i) for C1 = (R1R1^T) o Abar1; 1/deg2(l) per neighbour l for
+    C2 = (R2R2^T) o Abar2^T)."""
+    return (np.asarray(R_nbrs, dtype=np.float64) @ np.asarray(r_i, dtype=np.float64)) * np.asarray(scale,
+                                                                                                  dtype=np.float64)
+
+
+def cost_entry(S_block, c1_row, c2_row, inv1_nbr, inv2_nbr, c_node: float, anchored: bool,
+               logS_prev: float, p: Params) -> float:
+    """Eq. (2) plus the proximal term at one (i, j), with
+    S_block = S[N1(i)][:, N2(j)], c1_row[k] = C1[i, N1(i)_k], c2_row[l] = C2[j, N2(j)_l],
+    inv1_nbr[k] = Abar1[N1(i)_k, i] = 1/deg1(N1(i)_k), inv2_nbr[l] = Abar2[N2(j)_l, j]."""
+    S_block = np.asarray(S_block, dtype=np.float64)
+    E = float(np.asarray(c1_row, dtype=np.float64) @ S_block @ np.asarray(c2_row, dtype=np.float64))
+    P = float(np.asarray(inv1_nbr, dtype=np.float64) @ S_block @ np.asarray(inv2_nbr, dtype=np.float64))
+    anc = -np.log(p.ea + (1.0 if anchored else 0.0))
+    return float(c_node + p.lambda_e * E - p.lambda_n * np.log(P + p.delta_nbr) + p.lambda_a * anc
+                 - p.lp * logS_prev)
+
+
+def row_dual_entry(c_row, a, eps: float, n1: int) -> float:
+    """The b-update of Eq. (3) for one row i: eps log mu_i - eps LSE_j((a_j - C_ij)/eps)."""
+    x = (np.asarray(a, dtype=np.float64) - np.asarray(c_row, dtype=np.float64)) / eps
+    return float(eps * np.log(1.0 / n1) - eps * lse(x, axis=0))
+
+
+def plan_entry(c: float, a_j: float, b_i: float, eps: float) -> float:
+    """Eq. (4) at one (i, j)."""
+    return float(np.exp((a_j + b_i - c) / eps))

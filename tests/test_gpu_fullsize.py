@@ -1,0 +1,170 @@
+"""Parity at the full benchmark size (Chung-Lu n1 = n2 = 120,000, d = 128, 2,400
+anchors), in the launch configurations the benchmark times (the BF16 form with
+BF16 operands and plan, and the plain FP32 form; 17,856-row chunks of the SpMM
+intermediate): sampled outputs of every step against the FP64 oracle's
+single-entry forms, plus properties that hold at any size (row duals exact after
+a b-update, the reported marginal error, the argmax).
+
+Dense n1 x n2 matrices are 57.6 GB each, so the oracle never sees one: for each
+sampled (i, j) the test gathers the few operand entries that the output depends
+on (rows of the encodings, blocks of C or S over the two neighbourhoods) and
+evaluates the definition in FP64 on the host."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import fastalign_oracle as O
+from paper_2607_11952_amd.synth import CONFIGS, make_pair
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+CHUNK = 17856   # rows per chunk of the intermediate at n2 = 120,000 (the automatic choice of fa_align)
+NS = 48         # sampled entries per step
+
+
+def log(msg):
+    print(f"[fullsize] {msg}", flush=True)
+
+
+@pytest.fixture(scope="module")
+def setup(lib):
+    from paper_2607_11952_amd import api
+    cfg = CONFIGS["c5"]
+    pr = make_pair(cfg)
+    inp = api.AlignInputs.from_pair(pr)
+    rp1, ci1 = O.build_csr(pr.n1, pr.edges1)
+    rp2, ci2 = O.build_csr(pr.n2, pr.edges2)
+    assert np.array_equal(inp.A1.rowptr.cpu().numpy(), rp1) and np.array_equal(inp.A1.colidx.cpu().numpy(), ci1)
+    log(f"pair n1={pr.n1} n2={pr.n2} nnz1={rp1[-1]} nnz2={rp2[-1]}")
+    r = np.random.default_rng(2024)
+    i_s = r.integers(0, pr.n1, NS)
+    j_s = r.integers(0, pr.n2, NS)
+    # a third of the samples on true pairs, where the plan carries its mass
+    j_s[: NS // 3] = np.where(pr.truth[i_s[: NS // 3]] >= 0, pr.truth[i_s[: NS // 3]], j_s[: NS // 3])
+    return dict(api=api, cfg=cfg, pr=pr, inp=inp, rp1=rp1, ci1=ci1, rp2=rp2, ci2=ci2, i_s=i_s, j_s=j_s,
+                deg1=np.diff(rp1), deg2=np.diff(rp2))
+
+
+def _block(M, rows, cols):
+    dev = M.device
+    blk = M.index_select(0, torch.as_tensor(rows, dtype=torch.long, device=dev))
+    blk = blk.index_select(1, torch.as_tensor(cols, dtype=torch.long, device=dev))
+    return blk.double().cpu().numpy()
+
+
+def _entries(M, ii, jj):
+    dev = M.device
+    v = M[torch.as_tensor(ii, dtype=torch.long, device=dev), torch.as_tensor(jj, dtype=torch.long, device=dev)]
+    return v.double().cpu().numpy()
+
+
+@pytest.mark.parametrize("form", ["bf16", "f32"])
+def test_fullsize_phase1_cost_sinkhorn_plan(setup, form):
+    """form: the BF16 form (BF16 encodings/attributes and plan) or the plain FP32 form."""
+    s = setup
+    dt = torch.bfloat16 if form == "bf16" else torch.float32
+    plan_tol = 2.0 ** -8 if form == "bf16" else 2e-6
+    api, pr, inp = s["api"], s["pr"], s["inp"]
+    rp1, ci1, rp2, ci2, deg1, deg2 = s["rp1"], s["ci1"], s["rp2"], s["ci2"], s["deg1"], s["deg2"]
+    i_s, j_s = s["i_s"], s["j_s"]
+    eps, alpha = s["cfg"].eps, 0.5
+    n1, n2 = pr.n1, pr.n2
+
+    # ---- Phase 1: encodings, similarity, propagation
+    inv1, inv2 = api.row_normalize(inp.A1), api.row_normalize(inp.A2)
+    R1 = api.positional(inp.A1, inv1, inp.anchors[:, 0].contiguous(), 0.15, 10)
+    R2 = api.positional(inp.A2, inv2, inp.anchors[:, 1].contiguous(), 0.15, 10)
+    Xh1 = api.l2_normalize(inp.X1, dt)
+    Xh2 = api.l2_normalize(inp.X2, dt)
+    R1b, R2b = R1.to(dt), R2.to(dt)
+    C0 = api.feature_sim(Xh1, Xh2, R1b, R2b, alpha)
+    torch.cuda.synchronize()
+    got = _entries(C0, i_s, j_s)
+    f64 = lambda t, idx: t[torch.as_tensor(idx, dtype=torch.long, device=t.device)].double().cpu().numpy()
+    x1, x2, r1, r2 = f64(Xh1, i_s), f64(Xh2, j_s), f64(R1b, i_s), f64(R2b, j_s)
+    want = np.array([O.similarity_entry(x1[q], x2[q], r1[q], r2[q], alpha) for q in range(NS)])
+    assert np.allclose(got, want, rtol=2e-5, atol=1e-7), np.abs(got - want).max()
+    log(f"[{form}] similarity: max rel err {np.max(np.abs(got - want) / want):.2e}")
+
+    Cn = api.propagate(inp.A1, inv1, inp.A2, inv2, C0, 1, chunk_rows=CHUNK)
+    torch.cuda.synchronize()
+    got = _entries(Cn, i_s, j_s)
+    want = np.array([O.propagate_entry(_block(C0, ci1[rp1[i]:rp1[i + 1]], ci2[rp2[j]:rp2[j + 1]]), deg1[i], deg2[j])
+                     for i, j in zip(i_s, j_s)])
+    assert np.allclose(got, want, rtol=2e-6, atol=1e-9), np.abs(got - want).max()
+    log(f"propagation: max abs err {np.abs(got - want).max():.2e}")
+    del C0
+    torch.cuda.empty_cache()
+
+    # ---- Phase 3 on the node cost: a few Sinkhorn iterations, plan
+    a = torch.zeros(n2, dtype=torch.float64, device=Cn.device)
+    b = torch.zeros(n1, dtype=torch.float64, device=Cn.device)
+    api.sinkhorn(Cn, eps, a, b, 3)
+    S = api.plan(Cn, eps, a, b, dt)
+    torch.cuda.synchronize()
+    a_h, b_h = a.cpu().numpy(), b.cpu().numpy()
+    for i in i_s[:12]:
+        want = O.row_dual_entry(Cn[int(i)].double().cpu().numpy(), a_h, eps, n1)
+        assert abs(b_h[i] - want) <= 2e-8 + 1e-9 * abs(want), (i, b_h[i], want)
+    got = _entries(S, i_s, j_s)
+    cvals = _entries(Cn, i_s, j_s)
+    want = np.array([O.plan_entry(c, a_h[j], b_h[i], eps) for c, i, j in zip(cvals, i_s, j_s)])
+    assert np.all(np.abs(got - want) <= plan_tol * want + 1e-30), np.max(np.abs(got - want) / want)
+    log(f"Sinkhorn row duals and {form} plan entries ok")
+
+    # ---- Phase 2: cost rebuild from that plan (lambda_e scaled so C_edge is O(1))
+    S_blocks = [_block(S, ci1[rp1[i]:rp1[i + 1]], ci2[rp2[j]:rp2[j + 1]]) for i, j in zip(i_s, j_s)]
+    R1h = lambda idx: f64(R1, idx)
+    R2h = lambda idx: f64(R2, idx)
+    c1_rows, c2_rows = [], []
+    for i, j in zip(i_s, j_s):
+        n1i, n2j = ci1[rp1[i]:rp1[i + 1]], ci2[rp2[j]:rp2[j + 1]]
+        c1_rows.append(O.intra_row_entries(R1h([i])[0], R1h(n1i), 1.0 / max(deg1[i], 1)))
+        c2_rows.append(O.intra_row_entries(R2h([j])[0], R2h(n2j), 1.0 / deg2[n2j]))
+    E_s = [float(c1 @ Sb @ c2) for c1, Sb, c2 in zip(c1_rows, S_blocks, c2_rows)]
+    le = 1.0 / max(max(E_s), 1e-300)
+    p = api.params(eps=eps, lambda_e=le, chunk_rows=CHUNK, plan_dtype=form)
+    po = O.Params(eps=eps, lambda_e=le)
+    w1 = api.sddmm(inp.A1, inv1, R1, False)
+    w2 = api.sddmm(inp.A2, inv2, R2, True)
+    partner = torch.full((n1,), -1, dtype=torch.int32, device=Cn.device)
+    partner[inp.anchors[:, 0].long()] = inp.anchors[:, 1]
+    Cc = api.cost(inp.A1, inp.A2, w1, w2, inv1, inv2, S, Cn, partner, a, b, p, Cn)
+    torch.cuda.synchronize()
+    got = _entries(Cc, i_s, j_s)
+    anchored = set(map(tuple, pr.anchors.tolist()))
+    want = []
+    for q, (i, j) in enumerate(zip(i_s, j_s)):
+        logS = (a_h[j] + b_h[i] - cvals[q]) / eps
+        want.append(O.cost_entry(S_blocks[q], c1_rows[q], c2_rows[q], 1.0 / deg1[ci1[rp1[i]:rp1[i + 1]]],
+                                 1.0 / deg2[ci2[rp2[j]:rp2[j + 1]]], cvals[q], (int(i), int(j)) in anchored, logS, po))
+    want = np.array(want)
+    err = np.abs(got - want)
+    assert np.all(err <= 2e-6 * np.maximum(1.0, np.abs(want))), (err.max(), want[np.argmax(err)])
+    log(f"cost rebuild: max abs err {err.max():.2e} (|C| up to {np.abs(want).max():.1f})")
+    del S, Cn
+    torch.cuda.empty_cache()
+
+    # ---- Sinkhorn and plan on the rebuilt cost: row duals, reported marginal error, argmax
+    a.zero_()
+    b.zero_()
+    it, err_rep = api.sinkhorn(Cc, eps, a, b, 5)
+    S2, am = api.plan(Cc, eps, a, b, dt, argmax=True)
+    torch.cuda.synchronize()
+    assert it == 5
+    a_h, b_h = a.cpu().numpy(), b.cpu().numpy()
+    colsum = torch.zeros(n2, dtype=torch.float64, device=Cc.device)
+    for r0 in range(0, n1, 4096):
+        blk = Cc[r0:r0 + 4096].double()
+        colsum += torch.exp((a[None, :] + b[r0:r0 + 4096, None] - blk) / eps).sum(0)
+    err_ref = float((colsum - 1.0 / n2).abs().sum())
+    assert abs(err_rep - err_ref) <= 2e-6 * err_ref + 2e-7, (err_rep, err_ref)
+    am_h = am.cpu().numpy()
+    for i in i_s[:12]:
+        row = Cc[int(i)].double().cpu().numpy()
+        assert abs(O.row_dual_entry(row, a_h, eps, n1) - b_h[i]) <= 2e-8 + 1e-9 * abs(b_h[i])
+        y = a_h + b_h[i] - row
+        assert y[am_h[i]] >= y.max() - 1e-12 * max(1.0, abs(y.max())), (i, am_h[i], int(np.argmax(y)))
+    log(f"Sinkhorn on the rebuilt cost: reported error {err_rep:.6e}, recomputed {err_ref:.6e}; argmax ok")

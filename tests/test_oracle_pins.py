@@ -422,3 +422,40 @@ def test_planted_mistakes_are_caught(monkeypatch):
     P = M1.T @ S @ M2
     wrong = np.asarray((A2 @ (A1.T @ S).T).T)          # uses Abar2^T instead of Abar2
     assert np.allclose(O.nbr_product(A1, A2, S), P) and not np.allclose(wrong, P)
+
+
+def test_single_entry_forms_match_the_dense_oracle():
+    """The per-entry forms used for sampled checks at full size equal the dense steps
+    (themselves pinned above) at every sampled (i, j) of a small ragged pair."""
+    import dataclasses
+    cfg = dataclasses.replace(CONFIGS["c1"], n1=90, kind="chung_lu", keep_n2=70, anchor_frac=0.1, seed=41)
+    pr = make_pair(cfg)
+    p = O.Params(eps=0.1, outer_iters=1, inner_iters=5, k_r=4)
+    rp1, ci1 = O.build_csr(pr.n1, pr.edges1)
+    rp2, ci2 = O.build_csr(pr.n2, pr.edges2)
+    ph = O.phase1(pr.n1, rp1, ci1, pr.n2, rp2, ci2, pr.X1, pr.X2, pr.anchors, p)
+    X1h, X2h = O.l2_normalize_rows(pr.X1), O.l2_normalize_rows(pr.X2)
+    C0 = O.feature_similarity(pr.X1, pr.X2, ph["R1"], ph["R2"], p.alpha)
+    Cn = ph["C_node"]
+    deg1, deg2 = np.diff(rp1), np.diff(rp2)
+    r = rng(42)
+    S = r.random((pr.n1, pr.n2)) / (pr.n1 * pr.n2)
+    logS = np.log(S) + 0.3
+    C = O.cost_update(Cn, ph["C_anc"], ph["C1"], ph["C2"], ph["Abar1"], ph["Abar2"], S, logS, p)
+    a, b, _, _ = O.sinkhorn(C, p.eps, 3)
+    anchored = set(map(tuple, pr.anchors.tolist()))
+    for i, j in zip(r.integers(0, pr.n1, 60), r.integers(0, pr.n2, 60)):
+        n1i, n2j = ci1[rp1[i]:rp1[i + 1]], ci2[rp2[j]:rp2[j + 1]]
+        assert math.isclose(O.similarity_entry(X1h[i], X2h[j], ph["R1"][i], ph["R2"][j], p.alpha), C0[i, j],
+                            rel_tol=1e-12)
+        assert math.isclose(O.propagate_entry(C0[np.ix_(n1i, n2j)], deg1[i], deg2[j]), Cn[i, j], rel_tol=1e-12,
+                            abs_tol=1e-15)
+        c1 = O.intra_row_entries(ph["R1"][i], ph["R1"][n1i], 1.0 / max(deg1[i], 1))
+        c2 = O.intra_row_entries(ph["R2"][j], ph["R2"][n2j], 1.0 / deg2[n2j])
+        assert np.allclose(c1, ph["C1"][i].toarray()[0, n1i], rtol=1e-12)
+        assert np.allclose(c2, ph["C2"][j].toarray()[0, n2j], rtol=1e-12)
+        got = O.cost_entry(S[np.ix_(n1i, n2j)], c1, c2, 1.0 / deg1[n1i], 1.0 / deg2[n2j], Cn[i, j],
+                           (int(i), int(j)) in anchored, logS[i, j], p)
+        assert math.isclose(got, C[i, j], rel_tol=1e-11, abs_tol=1e-11)
+        assert math.isclose(O.row_dual_entry(C[i], a, p.eps, pr.n1), b[i], rel_tol=1e-12, abs_tol=1e-13)
+        assert math.isclose(O.plan_entry(C[i, j], a[j], b[i], p.eps), O.plan(C, a, b, p.eps)[i, j], rel_tol=1e-12)
