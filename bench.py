@@ -27,7 +27,8 @@ sys.path.insert(0, ROOT)
 
 METRIC = "align time (s) + SpMM HBM GB/s at n=120k: plain FP32 vs BF16+warm start @1e-6"
 HBM_PEAK_GBS = 8000.0
-KERNELS = ["lse_col_partial", "lse_col_merge", "lse_row", "cost_stage1", "cost_stage2", "plan"]
+KERNELS = ["lse_col_partial", "lse_col_merge", "lse_row", "cost_stage1", "cost_stage2", "plan", "featsim"]
+MFMA_PEAK_TFLOPS = {"bf16": 2500.0, "f32": 157.3}   # dense matrix-core peaks of the part
 
 
 def log(msg):
@@ -101,6 +102,8 @@ def algorithmic_bytes(kind, n1, n2, nnz1, nnz2, chunk, sbytes, zbytes):
         return 2 * zbytes * chunk * n2 + 12 * chunk * n2    # Z read + C_node, C_prev read + C written
     if kind == "plan":
         return (4 + sbytes) * N
+    if kind == "featsim":
+        return 4 * N          # C_node written once (operands are a few hundred MB)
     return 0
 
 
@@ -187,6 +190,12 @@ def main():
             by = algorithmic_bytes(name, pair.n1, pair.n2, inp.A1.nnz, inp.A2.nnz, chunk, sb, 4)
             out["kernels"][name] = dict(calls=calls, total_ms=st.kernel_ms[k], avg_ms=avg_ms,
                                         algorithmic_bytes=by, gbps=by / (avg_ms * 1e-3) / 1e9)
+            if name == "featsim":
+                fl = 2.0 * pair.n1 * pair.n2 * (pair.X1.shape[1] + len(pair.anchors))
+                fdt = "bf16" if p.feat_dtype == binding.FA_BF16 else "f32"
+                out["kernels"][name].update(flops=fl, tflops=fl / (avg_ms * 1e-3) / 1e12, dtype=fdt,
+                                            peak_tflops=MFMA_PEAK_TFLOPS[fdt],
+                                            frac_of_peak=fl / (avg_ms * 1e-3) / 1e12 / MFMA_PEAK_TFLOPS[fdt])
         return out
 
     # ---------------- headline form: warm-up steps, then K timed steps

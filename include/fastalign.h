@@ -99,9 +99,10 @@ typedef struct {
   double inner_err[64];
   /* with params.profile: summed device time and launch count per kernel class:
    * [0] column LSE partials, [1] column merge, [2] row LSE, [3] cost stage 1
-   * (left SpMM), [4] cost stage 2 (right SpMM + fused assembly), [5] plan */
-  double kernel_ms[6];
-  int32_t kernel_calls[6];
+   * (left SpMM), [4] cost stage 2 (right SpMM + fused assembly), [5] plan,
+   * [6] node similarity (MFMA GEMM) */
+  double kernel_ms[7];
+  int32_t kernel_calls[7];
 } fa_stats;
 
 /* Thread-local message describing the last non-OK status. */

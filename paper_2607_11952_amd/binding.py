@@ -49,7 +49,7 @@ class fa_stats(C.Structure):
         ("outer_done", C.c_int32), ("inner_total", C.c_int32), ("fell_back", C.c_int32),
         ("converged_all", C.c_int32), ("marg_err", C.c_double), ("phase_ms", C.c_double * 4),
         ("inner_iters", C.c_int32 * 64), ("inner_err", C.c_double * 64),
-        ("kernel_ms", C.c_double * 6), ("kernel_calls", C.c_int32 * 6),
+        ("kernel_ms", C.c_double * 7), ("kernel_calls", C.c_int32 * 7),
     ]
 
 

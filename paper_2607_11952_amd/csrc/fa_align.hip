@@ -218,7 +218,8 @@ extern "C" int fa_align(const fa_csr *A1, const fa_csr *A2, const float *X1, con
     R1op = B.Rb1;
     R2op = B.Rb2;
   }
-  FA_TRY(launch_feature_sim(B.Xh1, B.Xh2, n1, n2, d, fdt, R1op, R2op, nL, fdt, p->alpha, B.C_node, s));
+  FA_TIMED(tm, KK_FEATSIM, s,
+           FA_TRY(launch_feature_sim(B.Xh1, B.Xh2, n1, n2, d, fdt, R1op, R2op, nL, fdt, p->alpha, B.C_node, s)));
   FA_TRY(run_propagate(A1, B.inv1, A2, B.inv2, B.C_node, B.C, p->k_node, L.chunk_rows, B.zt, s));
 
   // ---------------- initial plan S0 = mu nu^T, written as the plan of C = eps*log(n1 n2), a = b = 0
