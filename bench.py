@@ -157,6 +157,15 @@ def main():
 
     truth = torch.from_numpy(pair.truth).to(dev).long()
     has_partner = truth >= 0
+    # ranking test set (§4): true pairs that are not anchors
+    test_truth = pair.truth.astype(np.int32).copy()
+    test_truth[pair.anchors[:, 0]] = -1
+    test_truth = torch.from_numpy(test_truth).to(dev)
+
+    def ranking(rank):
+        r = rank[rank > 0].double()
+        return dict(hits_at_1=float((r <= 1).double().mean()), hits_at_10=float((r <= 10).double().mean()),
+                    mrr=float((1.0 / r).mean()), test_pairs=int(r.numel()))
 
     def accuracy(am):
         """Share of the nodes of G1 with a true partner in G2 whose argmax is that partner."""
@@ -199,7 +208,7 @@ def main():
         return out
 
     # ---------------- headline form: warm-up steps, then K timed steps
-    al = api.Aligner(inp, p_head, mlp)
+    al = api.Aligner(inp, p_head, mlp, test_truth)
     log(f"[bench] headline form: workspace {al.ws_bytes / 2**30:.1f} GiB, plan {al.S.numel() * al.S.element_size() / 2**30:.1f} GiB")
     for w in range(args.warmup):
         timed_run(al)
@@ -211,6 +220,7 @@ def main():
         log(f"[bench] step {k + 1}/{args.steps}: {ms / 1e3:.3f} s, inner iterations {res.stats.inner_total}, "
             f"marginal error {res.stats.marg_err:.2e}")
     head = summarize(res, times[-1], p_head)
+    head["ranking"] = ranking(res.rank)
     head_argmax = res.argmax.clone()
     ms_step = float(np.mean(times))
     del al, res
@@ -220,9 +230,10 @@ def main():
     plain = None
     agree = None
     if not args.no_plain:
-        al = api.Aligner(inp, p_plain)
+        al = api.Aligner(inp, p_plain, None, test_truth)
         res, ms = timed_run(al)
         plain = summarize(res, ms, p_plain)
+        plain["ranking"] = ranking(res.rank)
         agree = float((res.argmax == head_argmax).float().mean().item())
         plain["accuracy_vs_truth"] = accuracy(res.argmax)
         log(f"[bench] plain FP32: {ms / 1e3:.3f} s, inner iterations {res.stats.inner_total}, "

@@ -225,9 +225,14 @@ int fa_sinkhorn(const float *C, int32_t n1, int32_t n2, double eps, double *a, d
 
 /* Plan recovery S_ij = exp((a_j + b_i - C_ij)/eps) (Eq. (4)) stored as s_dtype
  * (FA_F32 or FA_BF16, round-to-nearest-even).  If argmax is non-NULL it also
- * writes argmax_j (a_j + b_i - C_ij) per row i (lowest j on ties), int32[n1]. */
+ * writes argmax_j (a_j + b_i - C_ij) per row i (lowest j on ties), int32[n1].
+ * If truth (int32[n1], the true partner of row i in [0, n2), anything else = none)
+ * is non-NULL, rank (int32[n1], out) receives 1 + #{j : S_ij > S_i,truth_i} computed
+ * on the exact FP64 exponents in the same pass (the ranking behind Hits@K and MRR,
+ * §4), or 0 for rows without a partner.  truth and rank are both NULL or both set. */
 int fa_plan(const float *C, int32_t n1, int32_t n2, double eps, const double *a,
-            const double *b, void *S, int32_t s_dtype, int32_t *argmax, void *stream);
+            const double *b, void *S, int32_t s_dtype, int32_t *argmax, const int32_t *truth,
+            int32_t *rank, void *stream);
 
 /* ----------------------------------------------------------------------- */
 /* End to end (Algorithm 1)                                                  */
@@ -244,13 +249,15 @@ size_t fa_align_workspace_size(int32_t n1, int32_t n2, int32_t d, int32_t nL,
  *   mlp_weights float[fa_mlp_param_count()] or NULL; required if p->warm_start
  *   S_out [n1*n2] of p->plan_dtype (out): the final plan
  *   a_out double[n2], b_out double[n1], argmax_out int32[n1] (out)
+ *   truth int32[n1] / rank_out int32[n1]: optional (both or neither), the rank of
+ *     each row's true partner in the final plan, as in fa_plan
  *   stats host fa_stats (out), may be NULL
  * The call synchronises the stream once at the end to fill stats.  Returns
  * FA_WARN_NOT_CONVERGED if tol > 0 and some inner solve missed it. */
 int fa_align(const fa_csr *A1, const fa_csr *A2, const float *X1, const float *X2, int32_t d,
              const int32_t *anchors, int32_t nL, const fa_params *p, const float *mlp_weights,
-             void *S_out, double *a_out, double *b_out, int32_t *argmax_out, fa_stats *stats,
-             void *ws, size_t ws_bytes, void *stream);
+             void *S_out, double *a_out, double *b_out, int32_t *argmax_out, const int32_t *truth,
+             int32_t *rank_out, fa_stats *stats, void *ws, size_t ws_bytes, void *stream);
 
 /* ----------------------------------------------------------------------- */
 /* Learned warm start: per-node inputs and a 3-layer MLP                     */

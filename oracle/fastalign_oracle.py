@@ -56,6 +56,7 @@ __all__ = [
     "l2_normalize_rows", "feature_similarity", "propagate", "anchor_cost", "intra_costs",
     "cost_update", "lse", "sinkhorn", "plan", "marginal_error", "align",
     "similarity_entry", "propagate_entry", "intra_row_entries", "cost_entry", "row_dual_entry", "plan_entry",
+    "true_partner_ranks", "hits_at_k", "mean_reciprocal_rank",
 ]
 
 
@@ -374,3 +375,34 @@ def row_dual_entry(c_row, a, eps: float, n1: int) -> float:
 def plan_entry(c: float, a_j: float, b_i: float, eps: float) -> float:
     """Eq. (4) at one (i, j)."""
     return float(np.exp((a_j + b_i - c) / eps))
+
+
+# ----------------------------------------------------------------------------
+# Ranking readout of §4: Hits@K and MRR over the true partners
+# ----------------------------------------------------------------------------
+
+def true_partner_ranks(scores: np.ndarray, truth: np.ndarray) -> np.ndarray:
+    """Per row i with a true partner t = truth[i] in [0, n2): the rank of t among the
+    row's alignment scores, 1 + #{j : scores[i, j] > scores[i, t]}; 0 for other rows."""
+    scores = np.asarray(scores, dtype=np.float64)
+    n1, n2 = scores.shape
+    truth = np.asarray(truth, dtype=np.int64)
+    ranks = np.zeros(n1, dtype=np.int64)
+    for i in range(n1):
+        t = truth[i]
+        if 0 <= t < n2:
+            ranks[i] = 1 + int(np.count_nonzero(scores[i] > scores[i, t]))
+    return ranks
+
+
+def hits_at_k(ranks: np.ndarray, k: int) -> float:
+    """Share of the ranked rows (rank > 0) whose true partner is among the top k."""
+    r = np.asarray(ranks)
+    r = r[r > 0]
+    return float(np.mean(r <= k)) if r.size else 0.0
+
+
+def mean_reciprocal_rank(ranks: np.ndarray) -> float:
+    r = np.asarray(ranks, dtype=np.float64)
+    r = r[r > 0]
+    return float(np.mean(1.0 / r)) if r.size else 0.0

@@ -180,12 +180,17 @@ def sinkhorn(Cm: torch.Tensor, eps: float, a: torch.Tensor, b: torch.Tensor, max
     return hi.value, he.value
 
 
-def plan(Cm: torch.Tensor, eps: float, a: torch.Tensor, b: torch.Tensor, dtype=torch.float32, argmax: bool = False):
+def plan(Cm: torch.Tensor, eps: float, a: torch.Tensor, b: torch.Tensor, dtype=torch.float32, argmax: bool = False,
+         truth: Optional[torch.Tensor] = None):
+    """S (and argmax if asked; and the true partners' ranks if truth is given)."""
     n1, n2 = Cm.shape
     S = torch.empty((n1, n2), dtype=dtype, device=Cm.device)
     am = torch.empty(n1, dtype=torch.int32, device=Cm.device) if argmax else None
-    _lib().call("fa_plan", _ptr(Cm), n1, n2, float(eps), _ptr(a), _ptr(b), _ptr(S), _sdt(S), _ptr(am), _stream())
-    return (S, am) if argmax else S
+    rk = torch.empty(n1, dtype=torch.int32, device=Cm.device) if truth is not None else None
+    _lib().call("fa_plan", _ptr(Cm), n1, n2, float(eps), _ptr(a), _ptr(b), _ptr(S), _sdt(S), _ptr(am), _ptr(truth),
+                _ptr(rk), _stream())
+    out = (S,) + ((am,) if argmax else ()) + ((rk,) if truth is not None else ())
+    return out if len(out) > 1 else S
 
 
 # ------------------------------------------------------------------ end to end
@@ -215,6 +220,7 @@ class AlignResult:
     argmax: torch.Tensor
     stats: B.fa_stats
     status: int
+    rank: Optional[torch.Tensor] = None   # rank of each row's true partner (0: none), if asked for
 
 
 def workspace_bytes(inp: AlignInputs, p: B.fa_params) -> int:
@@ -225,8 +231,11 @@ def workspace_bytes(inp: AlignInputs, p: B.fa_params) -> int:
 class Aligner:
     """Holds the workspace and outputs for repeated fa_align calls on one input."""
 
-    def __init__(self, inp: AlignInputs, p: B.fa_params, mlp: Optional[torch.Tensor] = None):
-        self.inp, self.p, self.mlp = inp, p, mlp
+    def __init__(self, inp: AlignInputs, p: B.fa_params, mlp: Optional[torch.Tensor] = None,
+                 truth: Optional[torch.Tensor] = None):
+        """truth (int32[n1] on the device, -1 = no partner) makes run() also rank each
+        row's true partner in the final plan (AlignResult.rank)."""
+        self.inp, self.p, self.mlp, self.truth = inp, p, mlp, truth
         n1, n2 = inp.A1.n, inp.A2.n
         dev = inp.X1.device
         self.ws_bytes = workspace_bytes(inp, p)
@@ -236,6 +245,7 @@ class Aligner:
         self.a = torch.empty(n2, dtype=torch.float64, device=dev)
         self.b = torch.empty(n1, dtype=torch.float64, device=dev)
         self.argmax = torch.empty(n1, dtype=torch.int32, device=dev)
+        self.rank = torch.empty(n1, dtype=torch.int32, device=dev) if truth is not None else None
 
     def run(self) -> AlignResult:
         st = B.fa_stats()
@@ -243,12 +253,13 @@ class Aligner:
         status = _lib().call("fa_align", C.byref(inp.A1.c), C.byref(inp.A2.c), _ptr(inp.X1), _ptr(inp.X2),
                              int(inp.X1.shape[1]), _ptr(inp.anchors), int(inp.anchors.shape[0]), C.byref(self.p),
                              _ptr(self.mlp), _ptr(self.S), _ptr(self.a), _ptr(self.b), _ptr(self.argmax),
-                             C.byref(st), _ptr(self.ws), self.ws_bytes, _stream())
-        return AlignResult(self.S, self.a, self.b, self.argmax, st, status)
+                             _ptr(self.truth), _ptr(self.rank), C.byref(st), _ptr(self.ws), self.ws_bytes, _stream())
+        return AlignResult(self.S, self.a, self.b, self.argmax, st, status, self.rank)
 
 
-def align(inp: AlignInputs, p: B.fa_params, mlp: Optional[torch.Tensor] = None) -> AlignResult:
-    return Aligner(inp, p, mlp).run()
+def align(inp: AlignInputs, p: B.fa_params, mlp: Optional[torch.Tensor] = None,
+          truth: Optional[torch.Tensor] = None) -> AlignResult:
+    return Aligner(inp, p, mlp, truth).run()
 
 
 # ------------------------------------------------------------------ warm start pieces

@@ -76,10 +76,10 @@ _SIGS = {
                           C.POINTER(fa_params), _P, _P, _SZ, _P]),
     "fa_sinkhorn_workspace_size": (_SZ, [_I32, _I32]),
     "fa_sinkhorn": (C.c_int, [_P, _I32, _I32, _D, _P, _P, _I32, _D, _I32, _P, _P, _P, _P, _P, _SZ, _P]),
-    "fa_plan": (C.c_int, [_P, _I32, _I32, _D, _P, _P, _P, _I32, _P, _P]),
+    "fa_plan": (C.c_int, [_P, _I32, _I32, _D, _P, _P, _P, _I32, _P, _P, _P, _P]),
     "fa_align_workspace_size": (_SZ, [_I32, _I32, _I32, _I32, _I64, _I64, C.POINTER(fa_params)]),
     "fa_align": (C.c_int, [C.POINTER(fa_csr), C.POINTER(fa_csr), _P, _P, _I32, _P, _I32, C.POINTER(fa_params),
-                           _P, _P, _P, _P, _P, C.POINTER(fa_stats), _P, _SZ, _P]),
+                           _P, _P, _P, _P, _P, _P, _P, C.POINTER(fa_stats), _P, _SZ, _P]),
     "fa_node_feature_dim": (_I32, []),
     "fa_node_features_workspace_size": (_SZ, [_I32]),
     "fa_node_features": (C.c_int, [C.POINTER(fa_csr), _P, _P, _I32, _P, _P, _I32, _P, _P, _SZ, _P]),

@@ -138,9 +138,10 @@ extern "C" size_t fa_align_workspace_size(int32_t n1, int32_t n2, int32_t d, int
 
 extern "C" int fa_align(const fa_csr *A1, const fa_csr *A2, const float *X1, const float *X2, int32_t d,
                         const int32_t *anchors, int32_t nL, const fa_params *p, const float *mlp_weights, void *S_out,
-                        double *a_out, double *b_out, int32_t *argmax_out, fa_stats *stats, void *ws,
-                        size_t ws_bytes, void *stream) {
+                        double *a_out, double *b_out, int32_t *argmax_out, const int32_t *truth,
+                        int32_t *rank_out, fa_stats *stats, void *ws, size_t ws_bytes, void *stream) {
   FA_TRY(validate(A1, A2, d, nL, p));
+  FA_REQUIRE((truth == nullptr) == (rank_out == nullptr), FA_ERR_ARG, "fa_align: truth and rank_out go together");
   const int32_t n1 = A1->n, n2 = A2->n;
   FA_REQUIRE(S_out && a_out && b_out && argmax_out, FA_ERR_ARG, "fa_align: null output");
   FA_REQUIRE(d == 0 || (X1 && X2), FA_ERR_ARG, "fa_align: null attributes with d = %d", d);
@@ -227,7 +228,7 @@ extern "C" int fa_align(const fa_csr *A1, const fa_csr *A2, const float *X1, con
   FA_TRY(launch_fill_f64(a_out, n2, 0.0, s));
   FA_TRY(launch_fill_f64(b_out, n1, 0.0, s));
   FA_TRY(launch_fill_f32(B.C, static_cast<int64_t>(N), static_cast<float>(p->eps * log(static_cast<double>(n1) * n2)), s));
-  FA_TRY(run_plan(B.C, n1, n2, p->eps, a_out, b_out, S_out, p->plan_dtype, nullptr, s));
+  FA_TRY(run_plan(B.C, n1, n2, p->eps, a_out, b_out, S_out, p->plan_dtype, nullptr, nullptr, nullptr, s));
   if (p->warm_start) {
     FA_TRY(run_node_features(A1, B.inv1, X1, d, nullptr, B.nodes1, nL, B.feat, B.nf_ws, node_features_ws_bytes(n1),
                              s));
@@ -258,7 +259,8 @@ extern "C" int fa_align(const fa_csr *A1, const fa_csr *A2, const float *X1, con
     FA_TRY(run_sinkhorn(B.C, n1, n2, p->eps, a_out, b_out, p->inner_iters, p->tol, p->check_every, it_slot, er_slot,
                         B.sink, s, tm));
     FA_HIP(hipEventRecord(ev[2], s));
-    FA_TRY(run_plan(B.C, n1, n2, p->eps, a_out, b_out, S_out, p->plan_dtype, t == T - 1 ? argmax_out : nullptr, s,
+    FA_TRY(run_plan(B.C, n1, n2, p->eps, a_out, b_out, S_out, p->plan_dtype, t == T - 1 ? argmax_out : nullptr,
+                    t == T - 1 ? truth : nullptr, t == T - 1 ? rank_out : nullptr, s,
                     tm));
     FA_HIP(hipEventRecord(ev[3], s));
     // Per-outer timing costs one event wait per outer iteration (the loop is
@@ -273,7 +275,7 @@ extern "C" int fa_align(const fa_csr *A1, const fa_csr *A2, const float *X1, con
     t_plan += x;
     if (tm) tm->collect();
   }
-  if (T == 0) FA_TRY(run_plan(B.C, n1, n2, p->eps, a_out, b_out, S_out, p->plan_dtype, argmax_out, s));
+  if (T == 0) FA_TRY(run_plan(B.C, n1, n2, p->eps, a_out, b_out, S_out, p->plan_dtype, argmax_out, truth, rank_out, s));
   ms_cost = t_cost;
   ms_sink = t_sink;
   ms_plan = t_plan;

@@ -62,7 +62,8 @@ int run_sinkhorn(const float *C, int32_t n1, int32_t n2, double eps, double *a, 
                  int32_t max_iter, double tol, int32_t check_every, int32_t *dev_iters, double *dev_err,
                  SinkWs &w, hipStream_t s, KTimer *tm = nullptr);
 int run_plan(const float *C, int32_t n1, int32_t n2, double eps, const double *a, const double *b, void *S,
-             int32_t sdt, int32_t *argmax, hipStream_t s, KTimer *tm = nullptr);
+             int32_t sdt, int32_t *argmax, const int32_t *truth, int32_t *rank, hipStream_t s,
+             KTimer *tm = nullptr);
 
 // Warm start.
 int run_node_features(const fa_csr *A, const float *inv_deg, const float *X, int32_t d, const float *proj,

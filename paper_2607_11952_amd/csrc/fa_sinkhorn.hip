@@ -399,24 +399,37 @@ __device__ inline float exp2_split(double y) {
 }
 
 // Plan S = exp2((a_j + b_i - C_ij) * log2(e)/eps), optional row argmax of the FP64 exponent.
+// With truth/rank: the rank of each row's true partner t among the row's scores,
+// 1 + #{j : y_ij > y_it} (the §4 ranking behind Hits@K and MRR), counted in the
+// same pass on the FP64 exponents; y_it is formed with exactly the operations of
+// the main loop, so the partner never counts itself.  t outside [0, n2) gives 0.
 template <int V, typename TS>
 __global__ __launch_bounds__(256) void k_plan(const float *__restrict__ C, int32_t n1, int32_t n2,
                                               const double *__restrict__ a, const double *__restrict__ b, double k2,
-                                              TS *__restrict__ S, int32_t *__restrict__ argmax) {
+                                              TS *__restrict__ S, int32_t *__restrict__ argmax,
+                                              const int32_t *__restrict__ truth, int32_t *__restrict__ rank) {
   constexpr int R = 4;
   const int i0 = blockIdx.x * R;
-  double bk[R], best[R];
-  int bidx[R];
+  double bk[R], best[R], yt[R];
+  int bidx[R], tr[R], cnt[R];
 #pragma unroll
   for (int r = 0; r < R; ++r) {
     bk[r] = (i0 + r < n1) ? b[i0 + r] * k2 : 0.0;
     best[r] = -INFINITY;
     bidx[r] = 0x7fffffff;
+    tr[r] = (truth && i0 + r < n1) ? truth[i0 + r] : -1;
+    if (tr[r] >= n2) tr[r] = -1;
+    // the score is two explicit fmas here and in the main loop, so the compiler
+    // has no multiply-add left to contract differently in the two places
+    yt[r] = tr[r] >= 0 ? fma(-static_cast<double>(C[static_cast<int64_t>(i0 + r) * n2 + tr[r]]), k2,
+                             fma(a[tr[r]], k2, bk[r]))
+                       : INFINITY;
+    cnt[r] = 0;
   }
   for (int j = threadIdx.x * V; j < n2; j += 256 * V) {
-    double ak[V];
+    double aj[V];
 #pragma unroll
-    for (int v = 0; v < V; ++v) ak[v] = a[j + v] * k2;
+    for (int v = 0; v < V; ++v) aj[v] = a[j + v];
     float cr[R][V];
 #pragma unroll
     for (int r = 0; r < R; ++r) Vec<V>::load(C + static_cast<int64_t>(min(i0 + r, n1 - 1)) * n2 + j, cr[r]);
@@ -428,8 +441,9 @@ __global__ __launch_bounds__(256) void k_plan(const float *__restrict__ C, int32
       float sv[V];
 #pragma unroll
       for (int v = 0; v < V; ++v) {
-        const double y = fma(-static_cast<double>(c[v]), k2, ak[v] + bk[r]);
+        const double y = fma(-static_cast<double>(c[v]), k2, fma(aj[v], k2, bk[r]));
         sv[v] = exp2_split(y);
+        cnt[r] += y > yt[r];
         if (y > best[r]) {
           best[r] = y;
           bidx[r] = j + v;
@@ -438,10 +452,25 @@ __global__ __launch_bounds__(256) void k_plan(const float *__restrict__ C, int32
       VStore<TS, V>::run(S + base, sv);
     }
   }
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (rank) {
+    __shared__ int sc[R][4];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      int c = cnt[r];
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o, 64);
+      if (lane == 0) sc[r][w] = c;
+    }
+    __syncthreads();
+    if (threadIdx.x < R && i0 + static_cast<int>(threadIdx.x) < n1) {
+      const int r = threadIdx.x;
+      rank[i0 + r] = tr[r] >= 0 ? 1 + ((sc[r][0] + sc[r][1]) + (sc[r][2] + sc[r][3])) : 0;
+    }
+  }
   if (!argmax) return;
   __shared__ double sb[R][4];
   __shared__ int si[R][4];
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
 #pragma unroll
   for (int r = 0; r < R; ++r) {
     double v = best[r];
@@ -475,7 +504,7 @@ __global__ __launch_bounds__(256) void k_plan(const float *__restrict__ C, int32
 }
 
 int run_plan(const float *C, int32_t n1, int32_t n2, double eps, const double *a, const double *b, void *S,
-             int32_t sdt, int32_t *argmax, hipStream_t s, KTimer *tm) {
+             int32_t sdt, int32_t *argmax, const int32_t *truth, int32_t *rank, hipStream_t s, KTimer *tm) {
   if (n1 == 0 || n2 == 0) return FA_OK;
   const int tid = tm ? tm->begin(KK_PLAN, s) : -1;
   const double k2 = kLog2e / eps;
@@ -483,14 +512,14 @@ int run_plan(const float *C, int32_t n1, int32_t n2, double eps, const double *a
   const bool v4 = n2 % 4 == 0;
   if (sdt == FA_BF16) {
     if (v4)
-      FA_LAUNCH((k_plan<4, uint16_t>), g, dim3(256), 0, s, C, n1, n2, a, b, k2, static_cast<uint16_t *>(S), argmax);
+      FA_LAUNCH((k_plan<4, uint16_t>), g, dim3(256), 0, s, C, n1, n2, a, b, k2, static_cast<uint16_t *>(S), argmax, truth, rank);
     else
-      FA_LAUNCH((k_plan<1, uint16_t>), g, dim3(256), 0, s, C, n1, n2, a, b, k2, static_cast<uint16_t *>(S), argmax);
+      FA_LAUNCH((k_plan<1, uint16_t>), g, dim3(256), 0, s, C, n1, n2, a, b, k2, static_cast<uint16_t *>(S), argmax, truth, rank);
   } else {
     if (v4)
-      FA_LAUNCH((k_plan<4, float>), g, dim3(256), 0, s, C, n1, n2, a, b, k2, static_cast<float *>(S), argmax);
+      FA_LAUNCH((k_plan<4, float>), g, dim3(256), 0, s, C, n1, n2, a, b, k2, static_cast<float *>(S), argmax, truth, rank);
     else
-      FA_LAUNCH((k_plan<1, float>), g, dim3(256), 0, s, C, n1, n2, a, b, k2, static_cast<float *>(S), argmax);
+      FA_LAUNCH((k_plan<1, float>), g, dim3(256), 0, s, C, n1, n2, a, b, k2, static_cast<float *>(S), argmax, truth, rank);
   }
   if (tm) tm->end(tid, s);
   return FA_OK;
@@ -528,10 +557,11 @@ extern "C" int fa_sinkhorn(const float *C, int32_t n1, int32_t n2, double eps, d
 }
 
 extern "C" int fa_plan(const float *C, int32_t n1, int32_t n2, double eps, const double *a, const double *b, void *S,
-                       int32_t s_dtype, int32_t *argmax, void *stream) {
+                       int32_t s_dtype, int32_t *argmax, const int32_t *truth, int32_t *rank, void *stream) {
   FA_REQUIRE(n1 >= 0 && n2 >= 0 && eps > 0, FA_ERR_ARG, "fa_plan: bad sizes or eps");
   FA_REQUIRE(s_dtype == FA_F32 || s_dtype == FA_BF16, FA_ERR_ARG, "fa_plan: s_dtype %d", s_dtype);
   if (n1 == 0 || n2 == 0) return FA_OK;
   FA_REQUIRE(C && a && b && S, FA_ERR_ARG, "fa_plan: null pointer");
-  return run_plan(C, n1, n2, eps, a, b, S, s_dtype, argmax, static_cast<hipStream_t>(stream));
+  FA_REQUIRE((truth == nullptr) == (rank == nullptr), FA_ERR_ARG, "fa_plan: truth and rank go together");
+  return run_plan(C, n1, n2, eps, a, b, S, s_dtype, argmax, truth, rank, static_cast<hipStream_t>(stream));
 }

@@ -306,6 +306,31 @@ def test_plan_and_argmax(api, n2):
     assert torch.equal(Sb.view(torch.int16), S.to(torch.bfloat16).view(torch.int16))
 
 
+@pytest.mark.parametrize("n2", [520, 517])
+def test_plan_ranks_of_true_partners(api, n2):
+    """Ranks fused into the plan pass, bit-exact against the oracle's ranking of the
+    FP64 scores (ties by construction included), rows without a partner and
+    out-of-range partners give 0; both plan dtypes."""
+    n1, eps = 333, 0.05
+    r = np.random.default_rng(n2 + 1)
+    C = (r.random((n1, n2)) * 3).astype(np.float32)
+    C[:, 10] = C[:, 11]                     # duplicate columns: exact ties
+    a = r.standard_normal(n2) * 0.1
+    a[11] = a[10]
+    b = r.standard_normal(n1) * 0.1
+    truth = r.integers(0, n2, n1).astype(np.int32)
+    truth[::7] = -1
+    truth[3] = n2 + 5
+    truth[4] = 11
+    at, bt = torch.from_numpy(a).cuda(), torch.from_numpy(b).cuda()
+    tt = torch.from_numpy(truth).cuda()
+    want = O.true_partner_ranks(a[None, :] + b[:, None] - C.astype(np.float64), truth)
+    for dt in (torch.float32, torch.bfloat16):
+        S, am, rk = api.plan(torch.from_numpy(C).cuda(), eps, at, bt, dtype=dt, argmax=True, truth=tt)
+        assert np.array_equal(_np(rk), want)
+    assert want[3] == 0 and want[0] == 0 and want[4] >= 1
+
+
 def _align_both(api, pr, p, **kw):
     rp1, ci1 = O.build_csr(pr.n1, pr.edges1)
     rp2, ci2 = O.build_csr(pr.n2, pr.edges2)
@@ -340,6 +365,33 @@ def test_align_small_config_end_to_end(api):
     assert list(res.stats.inner_iters)[: cfg.outer_iters] == ref["iters"]
     for t in range(cfg.outer_iters):
         assert abs(res.stats.inner_err[t] - ref["errs"][t]) <= 1e-3 * ref["errs"][t] + 1e-8
+
+
+def test_align_ranks_hits_and_mrr(api):
+    """fa_align's ranking of the true partners (anchors excluded) on the small
+    workload: Hits@1, Hits@10 and MRR within 0.01 of the oracle's on its own final
+    plan, and every rank consistent with the returned FP32 plan."""
+    cfg = CONFIGS["c1"]
+    pr = make_pair(cfg)
+    p = O.Params(eps=cfg.eps, outer_iters=cfg.outer_iters, inner_iters=cfg.inner_iters)
+    rp1, ci1 = O.build_csr(pr.n1, pr.edges1)
+    rp2, ci2 = O.build_csr(pr.n2, pr.edges2)
+    ref = O.align(pr.n1, rp1, ci1, pr.n2, rp2, ci2, pr.X1, pr.X2, pr.anchors, p)
+    truth = pr.truth.astype(np.int32).copy()
+    truth[pr.anchors[:, 0]] = -1            # the test set: true pairs that are not anchors
+    want = O.true_partner_ranks(ref["S"], truth)
+    inp = api.AlignInputs.from_pair(pr)
+    res = api.align(inp, api.params(eps=p.eps, outer_iters=p.outer_iters, inner_iters=p.inner_iters),
+                    truth=torch.from_numpy(truth).cuda())
+    got = _np(res.rank)
+    assert np.array_equal(got > 0, want > 0)
+    for k in (1, 10):
+        assert abs(O.hits_at_k(got, k) - O.hits_at_k(want, k)) <= 0.01
+    assert abs(O.mean_reciprocal_rank(got) - O.mean_reciprocal_rank(want)) <= 0.01
+    S = _np(res.S).astype(np.float64)
+    lo = O.true_partner_ranks(S, truth)                                       # strictly larger in FP32
+    hi = np.array([1 + np.count_nonzero(S[i] >= S[i, t]) - 1 if t >= 0 else 0 for i, t in enumerate(truth)])
+    assert np.all((got >= lo) & (got <= hi))   # FP32 ties of S leave the exact rank anywhere in between
 
 
 def test_align_small_config_carried_duals(api):

@@ -459,3 +459,25 @@ def test_single_entry_forms_match_the_dense_oracle():
         assert math.isclose(got, C[i, j], rel_tol=1e-11, abs_tol=1e-11)
         assert math.isclose(O.row_dual_entry(C[i], a, p.eps, pr.n1), b[i], rel_tol=1e-12, abs_tol=1e-13)
         assert math.isclose(O.plan_entry(C[i, j], a[j], b[i], p.eps), O.plan(C, a, b, p.eps)[i, j], rel_tol=1e-12)
+
+
+def test_true_partner_ranks_vs_rankdata_and_closed_forms():
+    """Ranks equal scipy's 'min' ranking of the negated row (1 + number of strictly
+    larger scores), ties share the best rank, rows without a partner get 0;
+    Hits@K and MRR on hand-made ranks."""
+    import scipy.stats as ss
+    r = rng(50)
+    n1, n2 = 40, 23
+    scores = np.round(r.standard_normal((n1, n2)), 1)   # coarse values: ties occur
+    truth = r.integers(-3, n2 + 3, n1)
+    ranks = O.true_partner_ranks(scores, truth)
+    for i in range(n1):
+        t = truth[i]
+        if 0 <= t < n2:
+            assert ranks[i] == ss.rankdata(-scores[i], method="min")[t]
+        else:
+            assert ranks[i] == 0
+    assert (ranks > 0).any() and (ranks == 0).any()
+    rk = np.array([1, 2, 0, 10, 1, 4])
+    assert O.hits_at_k(rk, 1) == 2 / 5 and O.hits_at_k(rk, 4) == 4 / 5 and O.hits_at_k(rk, 10) == 1.0
+    assert math.isclose(O.mean_reciprocal_rank(rk), (1 + 0.5 + 0.1 + 1 + 0.25) / 5)
