@@ -122,7 +122,6 @@ static int validate(const fa_csr *A1, const fa_csr *A2, int32_t d, int32_t nL, c
              p->plan_dtype);
   FA_REQUIRE(p->feat_dtype == FA_F32 || p->feat_dtype == FA_BF16, FA_ERR_ARG, "fa_align: feat_dtype %d",
              p->feat_dtype);
-  FA_REQUIRE(nL <= 16384, FA_ERR_SHAPE, "fa_align: nL = %d above 16384", nL);
   return FA_OK;
 }
 

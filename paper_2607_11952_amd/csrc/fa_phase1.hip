@@ -110,6 +110,7 @@ __global__ void k_partner(const int32_t *__restrict__ anchors, const int32_t *__
 
 // SDDMM: one workgroup per row, the row's R vector staged in LDS, one wave per
 // neighbour at a time, deterministic wave reduction.
+template <bool STAGE>
 __global__ __launch_bounds__(256) void k_sddmm(const int64_t *__restrict__ rowptr,
                                                const int32_t *__restrict__ col,
                                                const float *__restrict__ inv_deg,
@@ -120,14 +121,19 @@ __global__ __launch_bounds__(256) void k_sddmm(const int64_t *__restrict__ rowpt
   const int64_t e0 = rowptr[i], e1 = rowptr[i + 1];
   if (e0 == e1) return;
   const float *Ri = R + static_cast<int64_t>(i) * nL;
-  for (int c = threadIdx.x; c < nL; c += 256) ri[c] = Ri[c];
-  __syncthreads();
+  // STAGE: row i of R in LDS (nL <= 16384); otherwise every wave reads it from
+  // global memory, where the workgroup's repeated reads hit the caches
+  const float *src = STAGE ? ri : Ri;
+  if (STAGE) {
+    for (int c = threadIdx.x; c < nL; c += 256) ri[c] = Ri[c];
+    __syncthreads();
+  }
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   for (int64_t e = e0 + w; e < e1; e += 4) {
     const int k = col[e];
     const float *Rk = R + static_cast<int64_t>(k) * nL;
     float acc = 0.f;
-    for (int c = lane; c < nL; c += 64) acc += ri[c] * Rk[c];
+    for (int c = lane; c < nL; c += 64) acc += src[c] * Rk[c];
     acc = wave_sum(acc);
     if (lane == 0) out[e] = acc * inv_deg[scale_by_col ? k : i];
   }
@@ -237,9 +243,11 @@ int launch_sddmm(const fa_csr *A, const float *inv_deg, const float *R, int32_t 
                  float *out, hipStream_t s) {
   if (A->n == 0 || A->nnz == 0) return FA_OK;
   if (nL == 0) return launch_fill_f32(out, A->nnz, 0.f, s);
-  FA_REQUIRE(static_cast<size_t>(nL) * 4 <= 64 * 1024, FA_ERR_SHAPE, "fa_sddmm: nL = %d too large (max 16384)", nL);
-  FA_LAUNCH(k_sddmm, dim3(A->n), dim3(256), sizeof(float) * nL, s, A->rowptr, A->colidx, inv_deg, R,
-            nL, by_col, out);
+  if (static_cast<size_t>(nL) * 4 <= 64 * 1024)
+    FA_LAUNCH(k_sddmm<true>, dim3(A->n), dim3(256), sizeof(float) * nL, s, A->rowptr, A->colidx, inv_deg, R,
+              nL, by_col, out);
+  else
+    FA_LAUNCH(k_sddmm<false>, dim3(A->n), dim3(256), 0, s, A->rowptr, A->colidx, inv_deg, R, nL, by_col, out);
   return FA_OK;
 }
 

@@ -1,0 +1,120 @@
+"""Erdos-Renyi scalability sweep of the whole method on one GPU.
+
+The paper's scalability experiments (§4, scalability analysis) align synthetic
+Erdos-Renyi pairs of average degree 10 from 10k to 110k nodes with 20% of the
+true pairs as anchors.  This sweep runs the same recipe through fa_align (seeded
+stand-ins: G2 a random relabelling with 5% edge noise, 32-dim attributes with
+N(0, 0.1^2) noise on G2, eps 0.05, 10 outer x 50 inner iterations) in both
+precision forms and records, per size: end-to-end time (HIP events, inputs
+resident), inner iterations, final marginal error, Hits@1 / Hits@10 / MRR over
+the non-anchor true pairs, and the device memory the call needs (workspace +
+plan), from which the largest n that fits in the device's memory follows.
+
+Usage: python -m paper_2607_11952_amd.scaling [--sizes 10000,20000,...] [--out sweep.json]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import sys
+import time
+
+import numpy as np
+import torch
+
+from . import api, binding
+from .synth import PairConfig, make_pair
+
+SIZES = [10000, 20000, 30000, 40000, 50000, 60000, 70000, 80000, 90000, 100000, 110000]
+
+
+def recipe(n: int) -> PairConfig:
+    return PairConfig(f"er{n // 1000}k", n, "er", 10.0, noise=0.05, d=32, sigma=0.1, anchor_frac=0.2, seed=7,
+                      eps=0.05, outer_iters=10, inner_iters=50)
+
+
+def device_bytes(inp: api.AlignInputs, p) -> int:
+    """Workspace plus plan of one fa_align call."""
+    n1, n2 = inp.A1.n, inp.A2.n
+    return api.workspace_bytes(inp, p) + n1 * n2 * (2 if p.plan_dtype == binding.FA_BF16 else 4)
+
+
+def largest_n(form: str, capacity: int) -> int:
+    """Largest n (n1 = n2, the sweep's recipe) whose fa_align call fits in `capacity` bytes
+    (bisection on the library's own workspace query; the CSR and attribute inputs add
+    well under 1% and are ignored)."""
+    lib = api._lib()
+    p = api.params(eps=0.05, plan_dtype=form, feat_dtype=form)
+    sb = 2 if form == "bf16" else 4
+
+    def need(n):
+        nnz = 10 * n
+        return lib.raw("fa_align_workspace_size")(n, n, 32, int(0.2 * n), nnz, nnz, p) + n * n * sb
+
+    lo, hi = 1000, 2_000_000
+    while hi - lo > 100:
+        mid = (lo + hi) // 2
+        if need(mid) <= capacity:
+            lo = mid
+        else:
+            hi = mid
+    return lo
+
+
+def run(sizes, forms=("bf16", "f32"), log=print):
+    dev = torch.device("cuda:0")
+    rows = []
+    for n in sizes:
+        cfg = recipe(n)
+        pr = make_pair(cfg)
+        inp = api.AlignInputs.from_pair(pr, dev)
+        truth = pr.truth.astype(np.int32).copy()
+        truth[pr.anchors[:, 0]] = -1
+        tt = torch.from_numpy(truth).to(dev)
+        for form in forms:
+            p = api.params(eps=cfg.eps, outer_iters=cfg.outer_iters, inner_iters=cfg.inner_iters, plan_dtype=form,
+                           feat_dtype=form)
+            al = api.Aligner(inp, p, None, tt)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            res = al.run()
+            e1.record()
+            torch.cuda.synchronize()
+            rk = res.rank[res.rank > 0].double()
+            row = dict(n=n, form=form, align_s=e0.elapsed_time(e1) / 1e3, inner_total=int(res.stats.inner_total),
+                       marg_err=float(res.stats.marg_err), hits_at_1=float((rk <= 1).double().mean()),
+                       hits_at_10=float((rk <= 10).double().mean()), mrr=float((1.0 / rk).mean()),
+                       device_gb=device_bytes(inp, p) / 1e9)
+            rows.append(row)
+            log(f"[sweep] n={n} {form}: {row['align_s']:.3f} s, Hits@1 {row['hits_at_1']:.4f}, "
+                f"MRR {row['mrr']:.4f}, {row['device_gb']:.1f} GB")
+            del al, res
+            torch.cuda.empty_cache()
+        del inp
+        torch.cuda.empty_cache()
+    cap = torch.cuda.get_device_properties(dev).total_memory
+    ceiling = {f: largest_n(f, int(cap * 0.97)) for f in forms}
+    return dict(recipe=dict(kind="er", avg_deg=10, noise=0.05, d=32, sigma=0.1, anchor_frac=0.2, eps=0.05,
+                            outer_iters=10, inner_iters=50),
+                rows=rows, device_memory_bytes=cap, largest_n_that_fits=ceiling)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--sizes", default=",".join(map(str, SIZES)))
+    ap.add_argument("--forms", default="bf16,f32")
+    ap.add_argument("--out", default="")
+    args = ap.parse_args()
+    log = lambda m: print(m, file=sys.stderr, flush=True)
+    t0 = time.time()
+    out = run([int(x) for x in args.sizes.split(",")], tuple(args.forms.split(",")), log=log)
+    out["seconds"] = time.time() - t0
+    if args.out:
+        with open(args.out, "w") as f:
+            json.dump(out, f, indent=1)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

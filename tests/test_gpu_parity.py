@@ -105,6 +105,23 @@ def test_sddmm_intra_costs(api, case):
     assert np.allclose(w2, C2.data, rtol=1e-5, atol=1e-9)
 
 
+def test_sddmm_many_anchors_unstaged(api):
+    """More than 16,384 anchor columns: the row of R is read from global memory
+    instead of LDS; values against the oracle's intra-network matrices."""
+    pr = make_case(200, None, 17, deg=6.0)
+    rp, ci = O.build_csr(pr.n1, pr.edges1)
+    A = api.DeviceCSR.from_host(pr.n1, rp, ci)
+    Abar, _ = O.row_normalized(pr.n1, rp, ci)
+    R = np.random.default_rng(3).random((pr.n1, 17000)) * 0.01
+    C1, C2 = O.intra_costs(R, Abar, R, Abar)
+    inv = api.row_normalize(A)
+    for by_col, M in ((False, C1), (True, C2)):
+        M = M.tocsr()
+        M.sort_indices()
+        got = _np(api.sddmm(A, inv, T32(R), by_col))
+        assert np.allclose(got, M.data, rtol=2e-5, atol=1e-9)
+
+
 @pytest.mark.parametrize("shape", [(300, 270, 40, 37), (129, 257, 0, 5), (64, 64, 32, 0), (1, 130, 3, 2),
                                    (300, 270, 40, 200), (257, 390, 96, 0)])
 def test_feature_sim_fp32(api, shape):
