@@ -27,7 +27,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "align time (s) + SpMM HBM GB/s at n=120k: plain FP32 vs BF16+warm start @1e-6"
 HBM_PEAK_GBS = 8000.0
-KERNELS = ["lse_col_partial", "lse_col_merge", "lse_row", "cost_stage1", "cost_stage2", "plan", "featsim"]
+KERNELS = ["lse_col_partial", "lse_col_merge", "lse_row", "cost_stage1", "cost_stage2", "plan", "featsim", "lse_col_t"]
 MFMA_PEAK_TFLOPS = {"bf16": 2500.0, "f32": 157.3}   # dense matrix-core peaks of the part
 
 
@@ -58,6 +58,7 @@ TRAFFIC = os.path.join(ROOT, "profiles", "traffic.json")
 
 # Kernel class -> the source file that defines it (with the shared headers).
 KERNEL_SOURCES = {"lse_col_partial": "fa_sinkhorn.hip", "lse_col_merge": "fa_sinkhorn.hip", "lse_row": "fa_sinkhorn.hip",
+                  "lse_col_t": "fa_sinkhorn.hip",
                   "plan": "fa_sinkhorn.hip", "cost_stage1": "fa_spmm.hip", "cost_stage2": "fa_spmm.hip"}
 
 
@@ -89,17 +90,18 @@ def measured_traffic(kernel, workload):
     return k.get("bytes_per_launch")
 
 
-def algorithmic_bytes(kind, n1, n2, nnz1, nnz2, chunk, sbytes, zbytes):
+def algorithmic_bytes(kind, n1, n2, nnz1, nnz2, chunk, sbytes, zbytes, transposed=True):
     """Compulsory HBM bytes per launch of each kernel class (see the design notes)."""
     N = n1 * n2
-    if kind in ("lse_col_partial", "lse_row"):
-        return 4 * N + 8 * (n1 + n2)                 # one FP32 pass over C + both dual vectors
+    if kind in ("lse_col_partial", "lse_row", "lse_col_t"):
+        return 4 * N + 8 * (n1 + n2)                 # one FP32 pass over C (or C^T) + both dual vectors
     if kind == "lse_col_merge":
         return 8 * n2 * 3
     if kind == "cost_stage1":
         return sbytes * n1 * n2 + 2 * zbytes * chunk * n2   # S read once + both Z sets written (one chunk)
     if kind == "cost_stage2":
-        return 2 * zbytes * chunk * n2 + 12 * chunk * n2    # Z read + C_node, C_prev read + C written
+        # Z read + C_node, C_prev read + C written (+ C^T written for the transposed column pass)
+        return 2 * zbytes * chunk * n2 + 12 * chunk * n2 + (4 * chunk * n2 if transposed else 0)
     if kind == "plan":
         return (4 + sbytes) * N
     if kind == "featsim":
@@ -196,7 +198,7 @@ def main():
             if calls == 0:
                 continue
             avg_ms = st.kernel_ms[k] / calls
-            by = algorithmic_bytes(name, pair.n1, pair.n2, inp.A1.nnz, inp.A2.nnz, chunk, sb, 4)
+            by = algorithmic_bytes(name, pair.n1, pair.n2, inp.A1.nnz, inp.A2.nnz, chunk, sb, 4, bool(p.transpose_cost))
             out["kernels"][name] = dict(calls=calls, total_ms=st.kernel_ms[k], avg_ms=avg_ms,
                                         algorithmic_bytes=by, gbps=by / (avg_ms * 1e-3) / 1e9)
             if name == "featsim":

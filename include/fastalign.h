@@ -85,6 +85,9 @@ typedef struct {
   int32_t carry_duals;/* 0: every inner solve starts from a = b = 0; 1: solves after the first
                          start from the previous solve's final duals.  The fixed point of each
                          solve is the same; only the iterates before convergence differ. */
+  int32_t transpose_cost; /* 1: fa_align keeps C^T beside C (one more n1*n2 FP32 buffer in
+                         the workspace) and runs the a-update on its rows; 0: column
+                         strips of C (less memory, a slower a-update) */
 } fa_params;
 
 /* Run statistics returned by fa_align (host struct). */
@@ -100,9 +103,9 @@ typedef struct {
   /* with params.profile: summed device time and launch count per kernel class:
    * [0] column LSE partials, [1] column merge, [2] row LSE, [3] cost stage 1
    * (left SpMM), [4] cost stage 2 (right SpMM + fused assembly), [5] plan,
-   * [6] node similarity (MFMA GEMM) */
-  double kernel_ms[7];
-  int32_t kernel_calls[7];
+   * [6] node similarity (MFMA GEMM), [7] column pass over C^T */
+  double kernel_ms[8];
+  int32_t kernel_calls[8];
 } fa_stats;
 
 /* Thread-local message describing the last non-OK status. */
@@ -196,11 +199,15 @@ int fa_propagate(const fa_csr *A1, const float *inv_deg1, const fa_csr *A2,
  *   partner int32[n1]: anchor partner in G2 of node i, or -1
  *   a double[n2], b double[n1]: duals that produced S from C_prev
  *   C_inout float[n1*n2]: C_prev in, C_new out (updated in place, row chunk by
- *   row chunk).  ws >= fa_cost_workspace_size(n1, n2, s_dtype, p->chunk_rows). */
+ *   row chunk).
+ *   Ct_out float[n2*n1] or NULL: if given, also receives C_new^T (row-major n2 x n1,
+ *   bit-identical to C_new), for fa_sinkhorn's transposed column pass.
+ *   ws >= fa_cost_workspace_size(n1, n2, s_dtype, p->chunk_rows). */
 int fa_cost(const fa_csr *A1, const fa_csr *A2, const float *w1, const float *w2,
             const float *inv_deg1, const float *inv_deg2, const void *S, int32_t s_dtype,
             const float *C_node, const int32_t *partner, const double *a, const double *b,
-            const fa_params *p, float *C_inout, void *ws, size_t ws_bytes, void *stream);
+            const fa_params *p, float *C_inout, float *Ct_out, void *ws, size_t ws_bytes,
+            void *stream);
 
 /* ----------------------------------------------------------------------- */
 /* Phase 3 (Eq. (3), Eq. (4))                                                */
@@ -216,9 +223,12 @@ size_t fa_sinkhorn_workspace_size(int32_t n1, int32_t n2);
  *   a double[n2], b double[n1]: starting duals in, final duals out
  *   dev_iters int32[1], dev_err double[1] (device, out): iterations done and the
  *   final marginal error.  The loop never waits for the host.
+ * Ct float[n2*n1] or NULL: C^T row-major.  If given, the a-update streams it
+ *   row by row (the pattern of the b-update) instead of column strips of C; the
+ *   results are the same up to summation order.
  * If host_iters/host_err are non-NULL the call synchronises the stream and
  * copies the two results to them. */
-int fa_sinkhorn(const float *C, int32_t n1, int32_t n2, double eps, double *a, double *b,
+int fa_sinkhorn(const float *C, const float *Ct, int32_t n1, int32_t n2, double eps, double *a, double *b,
                 int32_t max_iter, double tol, int32_t check_every, int32_t *dev_iters,
                 double *dev_err, int32_t *host_iters, double *host_err, void *ws,
                 size_t ws_bytes, void *stream);

@@ -88,7 +88,7 @@ def params(**kw) -> B.fa_params:
     for k, v in kw.items():
         if k in ("plan_dtype", "feat_dtype") and isinstance(v, str):
             v = {"f32": B.FA_F32, "bf16": B.FA_BF16}[v]
-        if k in ("feat_l2norm", "warm_start", "profile", "carry_duals"):
+        if k in ("feat_l2norm", "warm_start", "profile", "carry_duals", "transpose_cost"):
             v = int(v)
         setattr(p, k, v)
     if "lambda_p" not in kw:
@@ -156,26 +156,30 @@ def propagate(A1: DeviceCSR, inv1, A2: DeviceCSR, inv2, C_in: torch.Tensor, k: i
 
 # ------------------------------------------------------------------ Phase 2 / 3
 
-def cost(A1, A2, w1, w2, inv1, inv2, S, C_node, partner, a, b, p: B.fa_params, C_prev: torch.Tensor):
+def cost(A1, A2, w1, w2, inv1, inv2, S, C_node, partner, a, b, p: B.fa_params, C_prev: torch.Tensor,
+         transposed: bool = False):
+    """The rebuilt cost (a new tensor); with transposed=True also C^T: returns (C, Ct)."""
     Cm = C_prev.clone()
+    Ct = torch.empty((C_prev.shape[1], C_prev.shape[0]), dtype=torch.float32, device=Cm.device) if transposed else None
     nb = _lib().raw("fa_cost_workspace_size")(A1.n, A2.n, _sdt(S), p.chunk_rows)
     ws = torch.empty(max(nb, 1), dtype=torch.uint8, device=Cm.device)
     _lib().call("fa_cost", C.byref(A1.c), C.byref(A2.c), _ptr(w1), _ptr(w2), _ptr(inv1), _ptr(inv2), _ptr(S),
-                _sdt(S), _ptr(C_node), _ptr(partner), _ptr(a), _ptr(b), C.byref(p), _ptr(Cm), _ptr(ws), nb,
+                _sdt(S), _ptr(C_node), _ptr(partner), _ptr(a), _ptr(b), C.byref(p), _ptr(Cm), _ptr(Ct), _ptr(ws), nb,
                 _stream())
-    return Cm
+    return (Cm, Ct) if transposed else Cm
 
 
 def sinkhorn(Cm: torch.Tensor, eps: float, a: torch.Tensor, b: torch.Tensor, max_iter: int, tol: float = 0.0,
-             check_every: int = 1):
-    """Runs in place on a, b (FP64); returns (iterations, marginal error)."""
+             check_every: int = 1, Ct: Optional[torch.Tensor] = None):
+    """Runs in place on a, b (FP64); returns (iterations, marginal error).  Ct (C^T,
+    contiguous n2 x n1) selects the transposed column pass."""
     n1, n2 = Cm.shape
     nb = _lib().raw("fa_sinkhorn_workspace_size")(n1, n2)
     ws = torch.empty(nb, dtype=torch.uint8, device=Cm.device)
     di = torch.zeros(1, dtype=torch.int32, device=Cm.device)
     de = torch.zeros(1, dtype=torch.float64, device=Cm.device)
     hi, he = C.c_int32(0), C.c_double(0)
-    _lib().call("fa_sinkhorn", _ptr(Cm), n1, n2, float(eps), _ptr(a), _ptr(b), int(max_iter), float(tol),
+    _lib().call("fa_sinkhorn", _ptr(Cm), _ptr(Ct), n1, n2, float(eps), _ptr(a), _ptr(b), int(max_iter), float(tol),
                 int(check_every), _ptr(di), _ptr(de), C.byref(hi), C.byref(he), _ptr(ws), nb, _stream())
     return hi.value, he.value
 

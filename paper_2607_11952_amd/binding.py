@@ -41,6 +41,7 @@ class fa_params(C.Structure):
         ("feat_l2norm", C.c_int32), ("warm_start", C.c_int32), ("chunk_rows", C.c_int32),
         ("profile", C.c_int32),
         ("carry_duals", C.c_int32),
+        ("transpose_cost", C.c_int32),
     ]
 
 
@@ -49,7 +50,7 @@ class fa_stats(C.Structure):
         ("outer_done", C.c_int32), ("inner_total", C.c_int32), ("fell_back", C.c_int32),
         ("converged_all", C.c_int32), ("marg_err", C.c_double), ("phase_ms", C.c_double * 4),
         ("inner_iters", C.c_int32 * 64), ("inner_err", C.c_double * 64),
-        ("kernel_ms", C.c_double * 7), ("kernel_calls", C.c_int32 * 7),
+        ("kernel_ms", C.c_double * 8), ("kernel_calls", C.c_int32 * 8),
     ]
 
 
@@ -73,9 +74,9 @@ _SIGS = {
     "fa_cost_workspace_size": (_SZ, [_I32, _I32, _I32, _I32]),
     "fa_propagate": (C.c_int, [C.POINTER(fa_csr), _P, C.POINTER(fa_csr), _P, _P, _P, _I32, _I32, _P, _SZ, _P]),
     "fa_cost": (C.c_int, [C.POINTER(fa_csr), C.POINTER(fa_csr), _P, _P, _P, _P, _P, _I32, _P, _P, _P, _P,
-                          C.POINTER(fa_params), _P, _P, _SZ, _P]),
+                          C.POINTER(fa_params), _P, _P, _P, _SZ, _P]),
     "fa_sinkhorn_workspace_size": (_SZ, [_I32, _I32]),
-    "fa_sinkhorn": (C.c_int, [_P, _I32, _I32, _D, _P, _P, _I32, _D, _I32, _P, _P, _P, _P, _P, _SZ, _P]),
+    "fa_sinkhorn": (C.c_int, [_P, _P, _I32, _I32, _D, _P, _P, _I32, _D, _I32, _P, _P, _P, _P, _P, _SZ, _P]),
     "fa_plan": (C.c_int, [_P, _I32, _I32, _D, _P, _P, _P, _I32, _P, _P, _P, _P]),
     "fa_align_workspace_size": (_SZ, [_I32, _I32, _I32, _I32, _I64, _I64, C.POINTER(fa_params)]),
     "fa_align": (C.c_int, [C.POINTER(fa_csr), C.POINTER(fa_csr), _P, _P, _I32, _P, _I32, C.POINTER(fa_params),

@@ -40,7 +40,7 @@ struct AlignBufs {
   uint16_t *Rb1, *Rb2;
   void *Xh1, *Xh2;
   float *w1, *w2;
-  float *C_node, *C;
+  float *C_node, *C, *Ct;  // Ct: C^T (n2 x n1) when p->transpose_cost
   void *zt;
   SinkWs sink;
   int32_t *st_iters;
@@ -89,6 +89,7 @@ static void carve_align(Cv &cv, int32_t n1, int32_t n2, int32_t d, int32_t nL, i
   b.w2 = T((float *)0, nnz2 + 1);
   b.C_node = T((float *)0, N);
   b.C = T((float *)0, N);
+  if (p->transpose_cost) b.Ct = T((float *)0, N);
   b.zt = T((char *)0, zt_bytes(L.chunk_rows, n2));
   b.sink.pm = nullptr;
   b.st_iters = T((int32_t *)0, 64);
@@ -239,7 +240,8 @@ extern "C" int fa_align(const fa_csr *A1, const fa_csr *A2, const float *X1, con
   ms_p1 = f;
 
   CostArgs c{A1, A2, B.w1, B.inv1, B.w2, B.inv2, S_out, p->plan_dtype, B.C_node, B.partner, a_out, b_out,
-             p->lambda_e, p->lambda_n, p->lambda_a, p->lambda_p, p->eps, p->eps_anchor, p->delta_nbr, B.C};
+             p->lambda_e, p->lambda_n, p->lambda_a, p->lambda_p, p->eps, p->eps_anchor, p->delta_nbr, B.C,
+             p->transpose_cost ? B.Ct : nullptr};
   // Events: ev[0] start of cost, ev[1] end of cost, ev[2] end of Sinkhorn, ev[3] end of plan.
   double t_cost = 0, t_sink = 0, t_plan = 0;
   for (int t = 0; t < T; ++t) {
@@ -255,8 +257,8 @@ extern "C" int fa_align(const fa_csr *A1, const fa_csr *A2, const float *X1, con
     }  // else: the previous solve's duals are the start
     int32_t *it_slot = B.st_iters + (t < 64 ? t : 63);
     double *er_slot = B.st_err + (t < 64 ? t : 63);
-    FA_TRY(run_sinkhorn(B.C, n1, n2, p->eps, a_out, b_out, p->inner_iters, p->tol, p->check_every, it_slot, er_slot,
-                        B.sink, s, tm));
+    FA_TRY(run_sinkhorn(B.C, p->transpose_cost ? B.Ct : nullptr, n1, n2, p->eps, a_out, b_out, p->inner_iters,
+                        p->tol, p->check_every, it_slot, er_slot, B.sink, s, tm));
     FA_HIP(hipEventRecord(ev[2], s));
     FA_TRY(run_plan(B.C, n1, n2, p->eps, a_out, b_out, S_out, p->plan_dtype, t == T - 1 ? argmax_out : nullptr,
                     t == T - 1 ? truth : nullptr, t == T - 1 ? rank_out : nullptr, s,

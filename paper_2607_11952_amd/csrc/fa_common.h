@@ -169,7 +169,7 @@ inline int ceil_div(int64_t a, int64_t b) { return static_cast<int>((a + b - 1) 
 // Optional per-kernel timing with HIP events recorded on the launch stream around
 // individual launches.  Events come from a fixed pool; collect() must be called
 // after the stream has reached the last recorded event.
-enum KernelKind { KK_COL_PARTIAL = 0, KK_COL_MERGE, KK_ROW, KK_STAGE1, KK_STAGE2, KK_PLAN, KK_FEATSIM, KK_COUNT };
+enum KernelKind { KK_COL_PARTIAL = 0, KK_COL_MERGE, KK_ROW, KK_STAGE1, KK_STAGE2, KK_PLAN, KK_FEATSIM, KK_COL_T, KK_COUNT };
 struct KTimer {
   static constexpr int kPool = 2048;
   hipEvent_t ev[kPool];

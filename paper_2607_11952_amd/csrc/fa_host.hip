@@ -48,6 +48,7 @@ extern "C" void fa_default_params(fa_params *p) {
   p->chunk_rows = 0;
   p->profile = 0;
   p->carry_duals = 0;
+  p->transpose_cost = 1;
 }
 
 extern "C" int fa_device_check(void) {

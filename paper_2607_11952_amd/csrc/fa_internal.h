@@ -41,6 +41,7 @@ struct CostArgs {
   const double *a, *b;
   double lambda_e, lambda_n, lambda_a, lambda_p, eps, eps_anchor, delta;
   float *C;
+  float *Ct;  // nullable: also write C^T (n2 x n1) for the transposed column pass
 };
 int run_cost(const CostArgs &c, int32_t chunk_rows, void *zt, hipStream_t s, KTimer *tm = nullptr);
 int run_propagate(const fa_csr *A1, const float *inv1, const fa_csr *A2, const float *inv2, float *C,
@@ -58,7 +59,8 @@ struct SinkWs {
 };
 size_t sinkhorn_ws_bytes(int32_t n1, int32_t n2);
 int carve_sinkhorn(Carver &cv, int32_t n1, int32_t n2, SinkWs &w);
-int run_sinkhorn(const float *C, int32_t n1, int32_t n2, double eps, double *a, double *b,
+// Ct (nullable): C^T, row-major n2 x n1; when given the column pass streams it row by row.
+int run_sinkhorn(const float *C, const float *Ct, int32_t n1, int32_t n2, double eps, double *a, double *b,
                  int32_t max_iter, double tol, int32_t check_every, int32_t *dev_iters, double *dev_err,
                  SinkWs &w, hipStream_t s, KTimer *tm = nullptr);
 int run_plan(const float *C, int32_t n1, int32_t n2, double eps, const double *a, const double *b, void *S,

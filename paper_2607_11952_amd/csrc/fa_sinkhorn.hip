@@ -30,8 +30,10 @@ struct SinkCtl {
   uint32_t arrive;  // last-block counter of the merge kernel
 };
 
+constexpr int kColTRowsPerWg = 8;  // columns (rows of C^T) per workgroup of the transposed column pass
+
 struct SinkLayout {
-  int V, ncolblk, nsplit, rows_per_split, nmerge;
+  int V, ncolblk, nsplit, rows_per_split, nmerge, ncolt;
 };
 
 static SinkLayout sink_layout(int32_t n1, int32_t n2) {
@@ -46,6 +48,7 @@ static SinkLayout sink_layout(int32_t n1, int32_t n2) {
   L.nsplit = want < 1 ? 1 : (want > maxs ? maxs : want);
   L.rows_per_split = ceil_div(n1 > 0 ? n1 : 1, L.nsplit);
   L.nmerge = ceil_div(n2, 64);
+  L.ncolt = ceil_div(n2, kColTRowsPerWg);
   return L;
 }
 
@@ -55,7 +58,7 @@ size_t sinkhorn_ws_bytes(int32_t n1, int32_t n2) {
   z.take<double>(static_cast<size_t>(L.nsplit) * n2);
   z.take<double>(static_cast<size_t>(L.nsplit) * n2);
   z.take<double>(n2);
-  z.take<double>(L.nmerge + 1);
+  z.take<double>((L.nmerge > L.ncolt ? L.nmerge : L.ncolt) + 1);
   z.take<SinkCtl>(1);
   z.take<double>(1);
   return z.off;
@@ -66,7 +69,7 @@ int carve_sinkhorn(Carver &cv, int32_t n1, int32_t n2, SinkWs &w) {
   w.pm = cv.take<double>(static_cast<size_t>(L.nsplit) * n2);
   w.ps = cv.take<double>(static_cast<size_t>(L.nsplit) * n2);
   w.a_next = cv.take<double>(n2);
-  w.errp = cv.take<double>(L.nmerge + 1);
+  w.errp = cv.take<double>((L.nmerge > L.ncolt ? L.nmerge : L.ncolt) + 1);
   w.ctl = reinterpret_cast<int32_t *>(cv.take<SinkCtl>(1));
   w.err = cv.take<double>(1);
   w.nsplit = L.nsplit;
@@ -197,39 +200,12 @@ __global__ __launch_bounds__(256) void k_lse_col_partial(const float *__restrict
   }
 }
 
-// Column pass, part 2: fold the partials of each column in a fixed order, form the
-// new a_j (into the other buffer) and the column's marginal violation; the last
-// workgroup to finish sums the violations in block order and applies the stop rule.
-// A workgroup takes 64 columns; four lanes per column fold every fourth split
-// each (one pass, online max), then lane group 0 folds the four results in order.
-__global__ __launch_bounds__(256) void k_lse_col_merge(int32_t n2, int32_t nsplit, const double *__restrict__ pm,
-                                                       const double *__restrict__ ps, double *__restrict__ bufA0,
-                                                       double *__restrict__ bufA1, int32_t cur, double eps,
-                                                       double log_nu, double nu, double *__restrict__ errp,
-                                                       SinkCtl *__restrict__ ctl, int32_t it, int32_t is_check,
-                                                       int32_t is_final, double tol, int32_t *__restrict__ out_iters,
-                                                       double *__restrict__ out_err) {
-  if (ctl->done) return;
-  const double *a = cur ? bufA1 : bufA0;
-  double *an = cur ? bufA0 : bufA1;
-  const int c = threadIdx.x & 63, g = threadIdx.x >> 6;
-  const int j = blockIdx.x * 64 + c;
-  double M = -INFINITY, S = 0.0;
-  if (j < n2)
-    for (int q = g; q < nsplit; q += 4)
-      lse2_merge(M, S, pm[static_cast<int64_t>(q) * n2 + j], ps[static_cast<int64_t>(q) * n2 + j]);
-  __shared__ double fm[4][64], fs[4][64];
-  fm[g][c] = M;
-  fs[g][c] = S;
-  __syncthreads();
-  double e = 0.0;
-  if (g == 0 && j < n2) {
-    for (int q = 1; q < 4; ++q) lse2_merge(M, S, fm[q][c], fs[q][c]);
-    const double l2 = M + log2(S);  // log2 of the column sum
-    an[j] = a[j] + eps * (log_nu - l2 * kLn2);
-    e = fabs(exp2(l2) - nu);
-  }
-  // deterministic block sum
+// Block-order sum of the per-column violations e (one value per thread, zero
+// where a thread owns no column) and, in the last workgroup to arrive, the
+// fixed-order total and the stop rule.  Called by every thread of the workgroup.
+__device__ inline void finish_error(double e, double *__restrict__ errp, SinkCtl *__restrict__ ctl, int32_t it,
+                                    int32_t is_check, int32_t is_final, double tol, int32_t cur,
+                                    int32_t *__restrict__ out_iters, double *__restrict__ out_err) {
   __shared__ double red[4];
   e = wave_sum(e);
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = e;
@@ -262,6 +238,75 @@ __global__ __launch_bounds__(256) void k_lse_col_merge(int32_t n2, int32_t nspli
       *out_iters = it;
     }
   }
+}
+
+// Block-order sum of e into errp[blockIdx.x] only (no arrival counter): for
+// grids too large for one same-address atomic per workgroup to stay cheap.
+__device__ inline void block_error(double e, double *__restrict__ errp) {
+  __shared__ double red[4];
+  e = wave_sum(e);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = e;
+  __syncthreads();
+  if (threadIdx.x == 0) errp[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+// One workgroup: the fixed-order total of nblk block partials and the stop rule.
+__global__ __launch_bounds__(256) void k_error_finish(const double *__restrict__ errp, int32_t nblk,
+                                                      SinkCtl *__restrict__ ctl, int32_t it, int32_t is_check,
+                                                      int32_t is_final, double tol, int32_t cur,
+                                                      int32_t *__restrict__ out_iters, double *__restrict__ out_err) {
+  if (ctl->done) return;
+  double t = 0.0;
+  for (int q = threadIdx.x; q < nblk; q += 256) t += errp[q];
+  __shared__ double red[4];
+  t = wave_sum(t);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = t;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const double err = (red[0] + red[1]) + (red[2] + red[3]);
+    *out_err = err;
+    if (is_final || (is_check && tol > 0.0 && err <= tol)) {
+      ctl->done = 1;
+      ctl->iters = it;
+      ctl->which = cur;
+      *out_iters = it;
+    }
+  }
+}
+
+// Column pass, part 2: fold the partials of each column in a fixed order, form the
+// new a_j (into the other buffer) and the column's marginal violation; the last
+// workgroup to finish sums the violations in block order and applies the stop rule.
+// A workgroup takes 64 columns; four lanes per column fold every fourth split
+// each (one pass, online max), then lane group 0 folds the four results in order.
+__global__ __launch_bounds__(256) void k_lse_col_merge(int32_t n2, int32_t nsplit, const double *__restrict__ pm,
+                                                       const double *__restrict__ ps, double *__restrict__ bufA0,
+                                                       double *__restrict__ bufA1, int32_t cur, double eps,
+                                                       double log_nu, double nu, double *__restrict__ errp,
+                                                       SinkCtl *__restrict__ ctl, int32_t it, int32_t is_check,
+                                                       int32_t is_final, double tol, int32_t *__restrict__ out_iters,
+                                                       double *__restrict__ out_err) {
+  if (ctl->done) return;
+  const double *a = cur ? bufA1 : bufA0;
+  double *an = cur ? bufA0 : bufA1;
+  const int c = threadIdx.x & 63, g = threadIdx.x >> 6;
+  const int j = blockIdx.x * 64 + c;
+  double M = -INFINITY, S = 0.0;
+  if (j < n2)
+    for (int q = g; q < nsplit; q += 4)
+      lse2_merge(M, S, pm[static_cast<int64_t>(q) * n2 + j], ps[static_cast<int64_t>(q) * n2 + j]);
+  __shared__ double fm[4][64], fs[4][64];
+  fm[g][c] = M;
+  fs[g][c] = S;
+  __syncthreads();
+  double e = 0.0;
+  if (g == 0 && j < n2) {
+    for (int q = 1; q < 4; ++q) lse2_merge(M, S, fm[q][c], fs[q][c]);
+    const double l2 = M + log2(S);  // log2 of the column sum
+    an[j] = a[j] + eps * (log_nu - l2 * kLn2);
+    e = fabs(exp2(l2) - nu);
+  }
+  finish_error(e, errp, ctl, it, is_check, is_final, tol, cur, out_iters, out_err);
 }
 
 // Row pass (b-update): R rows per workgroup, the a-values of a column chunk are
@@ -336,6 +381,85 @@ __global__ __launch_bounds__(256) void k_lse_row(const float *__restrict__ C, in
   }
 }
 
+// Column pass from the transposed cost Ct = C^T (n2 rows of length n1): the row
+// pass's streaming pattern (whole rows, R at a time) applied to columns, so the
+// a-update reads long contiguous runs instead of 4 KB pieces of many rows.
+// Computes the new a_j (into the other buffer) and the column's marginal
+// violation; k_error_finish then forms the total and applies the stop rule.
+template <int V, int R>
+__global__ __launch_bounds__(256) void k_lse_col_t(const float *__restrict__ Ct, int32_t n1, int32_t n2,
+                                                   double *__restrict__ bufA0, double *__restrict__ bufA1,
+                                                   int32_t cur, const double *__restrict__ b, double k2, double eps,
+                                                   double log_nu, double nu, double *__restrict__ errp,
+                                                   const SinkCtl *__restrict__ ctl) {
+  if (ctl->done) return;
+  const double *a = cur ? bufA1 : bufA0;
+  double *an = cur ? bufA0 : bufA1;
+  const int j0 = blockIdx.x * R;
+  double ak[R], m[R], s[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    ak[r] = (j0 + r < n2) ? a[j0 + r] * k2 : 0.0;
+    m[r] = -INFINITY;
+    s[r] = 0.0;
+  }
+  for (int i = threadIdx.x * V; i < n1; i += 256 * V) {
+    // the R row loads of Ct go out together; rows past n2 re-read row n2-1, their sums are dropped
+    float cr[R][V];
+#pragma unroll
+    for (int r = 0; r < R; ++r) Vec<V>::load(Ct + static_cast<int64_t>(min(j0 + r, n2 - 1)) * n1 + i, cr[r]);
+    double bk[V];
+#pragma unroll
+    for (int v = 0; v < V; ++v) bk[v] = b[i + v] * k2;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const float *c = cr[r];
+      double x[V];
+      double mx = -INFINITY;
+#pragma unroll
+      for (int v = 0; v < V; ++v) {
+        x[v] = fma(-static_cast<double>(c[v]), k2, bk[v] + ak[r]);
+        mx = fmax(mx, x[v]);
+      }
+      if (mx > m[r]) {
+        s[r] *= static_cast<double>(exp2f(static_cast<float>(m[r] - mx)));
+        m[r] = mx;
+      }
+      float t = 0.f;
+#pragma unroll
+      for (int v = 0; v < V; ++v) t += exp2f(static_cast<float>(x[v] - m[r]));
+      s[r] += static_cast<double>(t);
+    }
+  }
+  __shared__ double sm[R][4];
+  __shared__ double ss[R][4];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    double mr = m[r];
+    double sr = s[r];
+    wave_lse2(mr, sr);
+    if (lane == 0) {
+      sm[r][w] = mr;
+      ss[r][w] = sr;
+    }
+  }
+  __syncthreads();
+  double e = 0.0;
+  if (threadIdx.x < R) {
+    const int r = threadIdx.x, j = j0 + r;
+    if (j < n2) {
+      double M = sm[r][0];
+      double S = ss[r][0];
+      for (int q = 1; q < 4; ++q) lse2_merge(M, S, sm[r][q], ss[r][q]);
+      const double l2 = M + log2(S);  // log2 of the column sum of the current plan
+      an[j] = a[j] + eps * (log_nu - l2 * kLn2);
+      e = fabs(exp2(l2) - nu);
+    }
+  }
+  block_error(e, errp);
+}
+
 // Final a: copy the scratch buffer into the caller's a if it holds the result.
 __global__ void k_final_a(double *__restrict__ a, const double *__restrict__ alt, int32_t n2,
                           const SinkCtl *__restrict__ ctl) {
@@ -351,8 +475,8 @@ __global__ void k_sink_reset(SinkCtl *ctl) {
   ctl->arrive = 0u;
 }
 
-int run_sinkhorn(const float *C, int32_t n1, int32_t n2, double eps, double *a, double *b, int32_t max_iter,
-                 double tol, int32_t check_every, int32_t *dev_iters, double *dev_err, SinkWs &w,
+int run_sinkhorn(const float *C, const float *Ct, int32_t n1, int32_t n2, double eps, double *a, double *b,
+                 int32_t max_iter, double tol, int32_t check_every, int32_t *dev_iters, double *dev_err, SinkWs &w,
                  hipStream_t s, KTimer *tm) {
   SinkLayout L = sink_layout(n1, n2);
   SinkCtl *ctl = reinterpret_cast<SinkCtl *>(w.ctl);
@@ -365,17 +489,32 @@ int run_sinkhorn(const float *C, int32_t n1, int32_t n2, double eps, double *a, 
     const int cur = it & 1;
     const int is_final = it == max_iter;
     const int is_check = it > 0 && (it % check_every == 0);
-    if (L.V == 4)
-      FA_TIMED(tm, KK_COL_PARTIAL, s,
-               FA_LAUNCH((k_lse_col_partial<4, kColRowsPerStep>), gcol, dim3(256), 0, s, C, n1, n2, a, w.a_next, cur, b, k2,
-                         L.rows_per_split, w.pm, w.ps, ctl));
-    else
-      FA_TIMED(tm, KK_COL_PARTIAL, s,
-               FA_LAUNCH((k_lse_col_partial<1, kColRowsPerStep>), gcol, dim3(256), 0, s, C, n1, n2, a, w.a_next, cur, b, k2,
-                         L.rows_per_split, w.pm, w.ps, ctl));
-    FA_TIMED(tm, KK_COL_MERGE, s,
-             FA_LAUNCH(k_lse_col_merge, gmerge, dim3(256), 0, s, n2, L.nsplit, w.pm, w.ps, a, w.a_next, cur, eps,
-                       log_nu, nu, w.errp, ctl, it, is_check, is_final, tol, dev_iters, dev_err));
+    if (Ct) {
+      const dim3 gct(L.ncolt);
+      if (n1 % 4 == 0)
+        FA_TIMED(tm, KK_COL_T, s,
+                 FA_LAUNCH((k_lse_col_t<4, kColTRowsPerWg>), gct, dim3(256), 0, s, Ct, n1, n2, a, w.a_next, cur, b,
+                           k2, eps, log_nu, nu, w.errp, ctl));
+      else
+        FA_TIMED(tm, KK_COL_T, s,
+                 FA_LAUNCH((k_lse_col_t<1, kColTRowsPerWg>), gct, dim3(256), 0, s, Ct, n1, n2, a, w.a_next, cur, b,
+                           k2, eps, log_nu, nu, w.errp, ctl));
+      FA_TIMED(tm, KK_COL_MERGE, s,
+               FA_LAUNCH(k_error_finish, dim3(1), dim3(256), 0, s, w.errp, L.ncolt, ctl, it, is_check, is_final, tol,
+                         cur, dev_iters, dev_err));
+    } else {
+      if (L.V == 4)
+        FA_TIMED(tm, KK_COL_PARTIAL, s,
+                 FA_LAUNCH((k_lse_col_partial<4, kColRowsPerStep>), gcol, dim3(256), 0, s, C, n1, n2, a, w.a_next, cur, b, k2,
+                           L.rows_per_split, w.pm, w.ps, ctl));
+      else
+        FA_TIMED(tm, KK_COL_PARTIAL, s,
+                 FA_LAUNCH((k_lse_col_partial<1, kColRowsPerStep>), gcol, dim3(256), 0, s, C, n1, n2, a, w.a_next, cur, b, k2,
+                           L.rows_per_split, w.pm, w.ps, ctl));
+      FA_TIMED(tm, KK_COL_MERGE, s,
+               FA_LAUNCH(k_lse_col_merge, gmerge, dim3(256), 0, s, n2, L.nsplit, w.pm, w.ps, a, w.a_next, cur, eps,
+                         log_nu, nu, w.errp, ctl, it, is_check, is_final, tol, dev_iters, dev_err));
+    }
     if (is_final) break;
     if (L.V == 4)
       FA_TIMED(tm, KK_ROW, s,
@@ -534,7 +673,7 @@ extern "C" size_t fa_sinkhorn_workspace_size(int32_t n1, int32_t n2) {
   return sinkhorn_ws_bytes(n1, n2);
 }
 
-extern "C" int fa_sinkhorn(const float *C, int32_t n1, int32_t n2, double eps, double *a, double *b,
+extern "C" int fa_sinkhorn(const float *C, const float *Ct, int32_t n1, int32_t n2, double eps, double *a, double *b,
                            int32_t max_iter, double tol, int32_t check_every, int32_t *dev_iters, double *dev_err,
                            int32_t *host_iters, double *host_err, void *ws, size_t ws_bytes, void *stream) {
   FA_REQUIRE(n1 > 0 && n2 > 0, FA_ERR_SHAPE, "fa_sinkhorn: n1 = %d, n2 = %d must be positive", n1, n2);
@@ -547,7 +686,7 @@ extern "C" int fa_sinkhorn(const float *C, int32_t n1, int32_t n2, double eps, d
   SinkWs w;
   FA_TRY(carve_sinkhorn(cv, n1, n2, w));
   hipStream_t s = static_cast<hipStream_t>(stream);
-  FA_TRY(run_sinkhorn(C, n1, n2, eps, a, b, max_iter, tol, check_every, dev_iters, dev_err, w, s));
+  FA_TRY(run_sinkhorn(C, Ct, n1, n2, eps, a, b, max_iter, tol, check_every, dev_iters, dev_err, w, s));
   if (host_iters || host_err) {
     FA_HIP(hipStreamSynchronize(s));
     if (host_iters) FA_HIP(hipMemcpy(host_iters, dev_iters, sizeof(int32_t), hipMemcpyDeviceToHost));

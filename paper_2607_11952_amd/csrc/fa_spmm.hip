@@ -206,7 +206,8 @@ __global__ __launch_bounds__(512) void k_stage2(const int64_t *__restrict__ rowp
                                                 int32_t nrows, const float *__restrict__ C_node,
                                                 const int32_t *__restrict__ partner,
                                                 const double *__restrict__ a, const double *__restrict__ b,
-                                                CostCoef cf, float *__restrict__ out) {
+                                                CostCoef cf, float *__restrict__ out, float *__restrict__ outT,
+                                                int32_t n1t) {
   __shared__ double tile[kZtRows][65];
   const int lane = threadIdx.x & 63;
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -259,23 +260,41 @@ __global__ __launch_bounds__(512) void k_stage2(const int64_t *__restrict__ rowp
   }
   __syncthreads();
   const int j = j0 + lane;
-  if (j >= n2) return;
-  const double aj = COST ? a[j] : 0.0;
-  for (int rr = 0; rr < 8; ++rr) {
-    const int r = w * 8 + rr;
-    const int rloc = blk * kZtRows + r;
-    if (rloc >= nrows) break;
-    const int i = row0 + rloc;
-    const int64_t idx = static_cast<int64_t>(i) * n2 + j;
-    const double g = tile[r][lane];
-    if (COST) {
-      const double anc = partner[i] == j ? cf.anc_on : cf.anc_off;
-      const double v = static_cast<double>(ld_stream(C_node + idx)) + g + cf.la * anc +
-                       cf.kp * (static_cast<double>(ld_stream(out + idx)) - aj - b[i]);
-      st_stream(out + idx, static_cast<float>(v));
-    } else {
-      st_stream(out + idx, static_cast<float>(g));
+  float vt[8];
+  if (j < n2) {
+    const double aj = COST ? a[j] : 0.0;
+    for (int rr = 0; rr < 8; ++rr) {
+      const int r = w * 8 + rr;
+      const int rloc = blk * kZtRows + r;
+      if (rloc >= nrows) break;
+      const int i = row0 + rloc;
+      const int64_t idx = static_cast<int64_t>(i) * n2 + j;
+      const double g = tile[r][lane];
+      if (COST) {
+        const double anc = partner[i] == j ? cf.anc_on : cf.anc_off;
+        const double v = static_cast<double>(ld_stream(C_node + idx)) + g + cf.la * anc +
+                         cf.kp * (static_cast<double>(ld_stream(out + idx)) - aj - b[i]);
+        vt[rr] = static_cast<float>(v);
+        st_stream(out + idx, vt[rr]);
+      } else {
+        st_stream(out + idx, static_cast<float>(g));
+      }
     }
+  }
+  if (!COST || outT == nullptr) return;
+  // C^T: the assembled tile goes through LDS (reusing the FP64 tile's storage once
+  // every thread has read its entries) so that column j0+c of the tile leaves as 64
+  // consecutive floats of row j0+c of C^T.
+  __syncthreads();
+  float(*tt)[65] = reinterpret_cast<float(*)[65]>(&tile[0][0]);
+  if (j < n2)
+    for (int rr = 0; rr < 8 && blk * kZtRows + w * 8 + rr < nrows; ++rr) tt[w * 8 + rr][lane] = vt[rr];
+  __syncthreads();
+  const int i0 = row0 + blk * kZtRows;
+  for (int cc = 0; cc < 8; ++cc) {
+    const int c = w * 8 + cc;
+    if (j0 + c < n2 && blk * kZtRows + lane < nrows)
+      st_stream(outT + static_cast<int64_t>(j0 + c) * n1t + i0 + lane, tt[lane][c]);
   }
 }
 
@@ -312,7 +331,7 @@ static int cost_chunks(const CostArgs &c, int32_t chunk_rows, void *zt, hipStrea
     FA_TIMED(tm, KK_STAGE2, s,
              FA_LAUNCH((k_stage2<true>), dim3(ceil_div(n2, 64), nblk), dim3(512), 0, s, c.A2->rowptr,
                        c.A2->colidx, c.w2, c.inv2, nullptr, Za, Zb, n2, r0, nr, c.C_node, c.partner, c.a, c.b, cf,
-                       c.C));
+                       c.C, c.Ct, n1));
   }
   return FA_OK;
 }
@@ -344,7 +363,7 @@ int run_propagate(const fa_csr *A1, const float *inv1, const fa_csr *A2, const f
                   A1->colidx, nullptr, inv1, nullptr, src, n2, r0, nr, Z, nullptr);
       FA_LAUNCH((k_stage2<false>), dim3(ceil_div(n2, 64), nblk), dim3(512), 0, s, A2->rowptr,
                 A2->colidx, nullptr, nullptr, inv2, Z, nullptr, n2, r0, nr, nullptr, nullptr, nullptr,
-                nullptr, cf, dst);
+                nullptr, cf, dst, nullptr, n1);
     }
     float *t = src;
     src = dst;
@@ -387,7 +406,7 @@ extern "C" int fa_propagate(const fa_csr *A1, const float *inv_deg1, const fa_cs
 extern "C" int fa_cost(const fa_csr *A1, const fa_csr *A2, const float *w1, const float *w2, const float *inv_deg1,
                        const float *inv_deg2, const void *S, int32_t s_dtype, const float *C_node,
                        const int32_t *partner, const double *a, const double *b, const fa_params *p,
-                       float *C_inout, void *ws, size_t ws_bytes, void *stream) {
+                       float *C_inout, float *Ct_out, void *ws, size_t ws_bytes, void *stream) {
   FA_TRY(check_csr(A1, "fa_cost A1"));
   FA_TRY(check_csr(A2, "fa_cost A2"));
   FA_REQUIRE(p, FA_ERR_ARG, "fa_cost: null params");
@@ -402,6 +421,7 @@ extern "C" int fa_cost(const fa_csr *A1, const fa_csr *A2, const float *w1, cons
   FA_REQUIRE(ws && ws_bytes >= need, FA_ERR_WORKSPACE, "fa_cost: workspace %zu < %zu bytes", ws_bytes, need);
   hipStream_t s = static_cast<hipStream_t>(stream);
   CostArgs c{A1, A2, w1, inv_deg1, w2, inv_deg2, S, s_dtype, C_node, partner, a, b,
-             p->lambda_e, p->lambda_n, p->lambda_a, p->lambda_p, p->eps, p->eps_anchor, p->delta_nbr, C_inout};
+             p->lambda_e, p->lambda_n, p->lambda_a, p->lambda_p, p->eps, p->eps_anchor, p->delta_nbr, C_inout,
+             Ct_out};
   return run_cost(c, cr, ws, s);
 }

@@ -131,7 +131,7 @@ def test_fullsize_phase1_cost_sinkhorn_plan(setup, form):
     w2 = api.sddmm(inp.A2, inv2, R2, True)
     partner = torch.full((n1,), -1, dtype=torch.int32, device=Cn.device)
     partner[inp.anchors[:, 0].long()] = inp.anchors[:, 1]
-    Cc = api.cost(inp.A1, inp.A2, w1, w2, inv1, inv2, S, Cn, partner, a, b, p, Cn)
+    Cc, CcT = api.cost(inp.A1, inp.A2, w1, w2, inv1, inv2, S, Cn, partner, a, b, p, Cn, transposed=True)
     torch.cuda.synchronize()
     got = _entries(Cc, i_s, j_s)
     anchored = set(map(tuple, pr.anchors.tolist()))
@@ -150,7 +150,8 @@ def test_fullsize_phase1_cost_sinkhorn_plan(setup, form):
     # ---- Sinkhorn and plan on the rebuilt cost: row duals, reported marginal error, argmax
     a.zero_()
     b.zero_()
-    it, err_rep = api.sinkhorn(Cc, eps, a, b, 5)
+    it, err_rep = api.sinkhorn(Cc, eps, a, b, 5, Ct=CcT)   # the benchmark's column pass over C^T
+    del CcT
     S2, am = api.plan(Cc, eps, a, b, dt, argmax=True)
     torch.cuda.synchronize()
     assert it == 5

@@ -237,11 +237,18 @@ def test_cost_per_term(api, case, terms, sdt):
                        dev["C_node"], dev["partner"], dev["a"], dev["b"], cp, dev["Cprev"]))
     tol = 2e-6 * np.abs(want).max() + 1e-5
     if sdt == "bf16":
-        # the SpMM intermediates are stored in BF16 too: sums of non-negative terms,
-        # each rounded once (relative 2^-9) -> |dE| <= le*Emax*2^-8, |dlog P| <= 2^-8
+        # the oracle sees the BF16 plan itself; the FP32 intermediates add FP32
+        # rounding only.  Allowed: the BF16 form's stated bound with a factor 2,
+        # |dE| <= le*Emax*2^-8, |dlog P| <= 2^-8
         tol += lam[0] * Emax * 2.0 ** -8 + lam[1] * 2.0 ** -8
     err = np.abs(got - want).max()
     assert err <= tol, (terms, sdt, err, tol)
+    if terms == "all":
+        # the transposed copy for the column pass is the same values, bit for bit
+        C2, CT = api.cost(case["inp"].A1, case["inp"].A2, dev["w1"], dev["w2"], dev["inv1"], dev["inv2"], S_t,
+                          dev["C_node"], dev["partner"], dev["a"], dev["b"], cp, dev["Cprev"], transposed=True)
+        assert torch.equal(C2.view(torch.int32), T32(got).view(torch.int32))
+        assert torch.equal(CT.view(torch.int32), C2.t().contiguous().view(torch.int32))
 
 
 def _sinkhorn_case(n1, n2, seed, eps):
@@ -250,8 +257,10 @@ def _sinkhorn_case(n1, n2, seed, eps):
     return C
 
 
-@pytest.mark.parametrize("shape", [(600, 2500), (513, 301), (1, 7), (9, 1), (300, 2503)])
-def test_sinkhorn_fixed_iterations(api, shape):
+@pytest.mark.parametrize("transposed", [False, True], ids=["strips", "transposed"])
+@pytest.mark.parametrize("shape", [(600, 2500), (513, 301), (1, 7), (9, 1), (300, 2503), (2503, 300)])
+def test_sinkhorn_fixed_iterations(api, shape, transposed):
+    """Both column passes (strips of C, or rows of C^T); odd sizes take the scalar paths."""
     n1, n2 = shape
     eps = 0.05
     C = _sinkhorn_case(n1, n2, n1 + n2, eps)
@@ -260,7 +269,7 @@ def test_sinkhorn_fixed_iterations(api, shape):
     Ct = torch.from_numpy(C32).cuda()
     a = torch.zeros(n2, dtype=torch.float64, device="cuda")
     b = torch.zeros(n1, dtype=torch.float64, device="cuda")
-    it, err = api.sinkhorn(Ct, eps, a, b, 25)
+    it, err = api.sinkhorn(Ct, eps, a, b, 25, Ct=Ct.t().contiguous() if transposed else None)
     assert it == 25 == it_o
     S_o = O.plan(C32.astype(np.float64), a_o, b_o, eps)
     S_g = O.plan(C32.astype(np.float64), a.cpu().numpy(), b.cpu().numpy(), eps)
@@ -272,21 +281,23 @@ def test_sinkhorn_fixed_iterations(api, shape):
     assert abs(err - err_o) <= 1e-6 + 1e-3 * err_o
 
 
-def test_sinkhorn_two_by_two_closed_form(api):
+@pytest.mark.parametrize("transposed", [False, True], ids=["strips", "transposed"])
+def test_sinkhorn_two_by_two_closed_form(api, transposed):
     for delta, eps in [(0.3, 0.1), (-1.0, 0.25)]:
         C = torch.tensor([[delta, 0.0], [0.0, 0.0]], dtype=torch.float32, device="cuda")
         a = torch.zeros(2, dtype=torch.float64, device="cuda")
         b = torch.zeros(2, dtype=torch.float64, device="cuda")
         # the GPU evaluates the marginal error with FP32 exponentials of FP64-shifted
         # exponents: its resolution is ~2^-24 * |shift| * ln 2 relative per entry
-        it, err = api.sinkhorn(C, eps, a, b, 3000, tol=1e-7)
+        it, err = api.sinkhorn(C, eps, a, b, 3000, tol=1e-7, Ct=C.t().contiguous() if transposed else None)
         S = api.plan(C, eps, a, b).cpu().numpy()
         x = 1.0 / (2.0 * (1.0 + math.exp(delta / (2 * eps))))
         assert np.allclose(S, [[x, 0.5 - x], [0.5 - x, x]], atol=2e-7)
         assert err <= 1e-7 and it < 3000
 
 
-def test_sinkhorn_tolerance_stop_matches_oracle(api):
+@pytest.mark.parametrize("transposed", [False, True], ids=["strips", "transposed"])
+def test_sinkhorn_tolerance_stop_matches_oracle(api, transposed):
     n1, n2, eps = 200, 300, 0.2
     C = _sinkhorn_case(n1, n2, 3, eps) * 0.2
     C32 = C.astype(np.float32).astype(np.float64)
@@ -295,7 +306,7 @@ def test_sinkhorn_tolerance_stop_matches_oracle(api):
     Ct = T32(C32)
     a = torch.zeros(n2, dtype=torch.float64, device="cuda")
     b = torch.zeros(n1, dtype=torch.float64, device="cuda")
-    it, err = api.sinkhorn(Ct, eps, a, b, 5000, tol=tol, check_every=1)
+    it, err = api.sinkhorn(Ct, eps, a, b, 5000, tol=tol, check_every=1, Ct=Ct.t().contiguous() if transposed else None)
     assert err <= tol and abs(it - it_o) <= 1, (it, it_o, err, err_o)
     # marginal error evaluated independently in FP64 from the returned duals
     S = O.plan(C32, a.cpu().numpy(), b.cpu().numpy(), eps)
@@ -369,12 +380,14 @@ def _plan_close(S_gpu, S_ref, bound):
     return _plan_err(S_gpu, S_ref) <= bound
 
 
-def test_align_small_config_end_to_end(api):
-    """The small workload (ER n=1000, eps 0.05, 10 x 50): plan within 1e-4, argmax identical."""
+@pytest.mark.parametrize("transpose_cost", [1, 0], ids=["transposed", "strips"])
+def test_align_small_config_end_to_end(api, transpose_cost):
+    """The small workload (ER n=1000, eps 0.05, 10 x 50): plan within 1e-4, argmax identical,
+    with either column pass."""
     cfg = CONFIGS["c1"]
     pr = make_pair(cfg)
     p = O.Params(eps=cfg.eps, outer_iters=cfg.outer_iters, inner_iters=cfg.inner_iters)
-    ref, res = _align_both(api, pr, p)
+    ref, res = _align_both(api, pr, p, transpose_cost=transpose_cost)
     S = _np(res.S)
     assert _plan_close(S, ref["S"], 1e-4), np.abs(S - ref["S"]).max() / ref["S"].max()
     assert np.array_equal(_np(res.argmax), ref["argmax"])
