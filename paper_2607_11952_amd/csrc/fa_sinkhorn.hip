@@ -9,12 +9,17 @@
 //   b_i <- b_i + eps * (log mu_i - LSE_j((a_j + b_i - C_ij)/eps)),
 // which is Eq. (3) rewritten, so FP32 only ever sees well-scaled exponents.
 //
-// The column pass (a-update) reads row-major tiles: workgroups own a column strip
-// and a row range and leave a (max, sum) partial per column; a merge kernel folds
-// the partials in a fixed order (deterministic, no float atomics).  The same
-// merge yields the column sums of the current plan, i.e. the L1 marginal error
-// of the previous iteration, for free.  The row pass (b-update) gives each
-// workgroup four rows and reduces across the workgroup with wavefront shuffles.
+// Two forms of the column pass (a-update).  With a transposed copy C^T (written by
+// the cost rebuild) it streams rows of C^T exactly like the row pass streams rows
+// of C: R columns per workgroup, each workgroup leaves its share of the marginal
+// error and a one-workgroup kernel forms the total and the stop decision.
+// Without it, workgroups own a column strip and a row range of C and leave a
+// (max, sum) partial per column, and a merge kernel folds the partials in a fixed
+// order.  Either way the pass also yields the column sums of the current plan,
+// i.e. the L1 marginal error of the previous iteration, for free, and every
+// reduction runs in a fixed order (deterministic, no float atomics).  The row pass
+// (b-update) gives each workgroup eight rows and reduces across the workgroup with
+// wavefront shuffles.
 //
 // The loop never waits for the host: a device control word marks convergence and
 // every later kernel of the loop returns at its first instruction.

@@ -8,13 +8,16 @@
 //   C  <- C_node + le*E - ln*log(P + delta) + la*C_anc - lp*(a_j + b_i - C_prev)/eps
 //
 // Both stages read contiguous multi-hundred-byte segments: stage 1 writes Z in a
-// block-transposed layout Zt[block][l][r] (64 rows r of a row block stored
-// contiguously per column l), so stage 2's gather of column l of a row block is
-// one 256-byte segment.  The intermediate is FP32 in both precision forms: the
-// BF16 form halves the reads of S, and an FP32 intermediate costs no time (stage 1
-// is gather-bound, stage 2 accumulates in FP64) while keeping E and P accurate.  Neighbour lists are uniform
-// per wavefront (one output row or column per wave), so indices and weights come
-// through the scalar cache and no lane diverges on the power-law degrees.
+// block-transposed layout Zt[block][l][set][r] (64 rows r of a row block stored
+// contiguously per column l, the two value sets side by side), so stage 2's
+// gather of column l of a row block is one 512-byte piece.  The intermediate is
+// FP32 in both precision forms: the BF16 form halves the reads of S, and an FP32
+// intermediate keeps E and P accurate (both stages are bound by gather traffic
+// behind L2, stage 2 accumulates in FP64).  Neighbour lists are uniform per
+// wavefront (one output row or column per wave), fetched 64 at a time with one
+// coalesced load and broadcast lane by lane, so no lane diverges on the power-law
+// degrees.  With a C^T buffer, stage 2 also writes the transposed cost for the
+// Sinkhorn column pass.
 #include "fa_common.h"
 #include "fa_internal.h"
 
@@ -68,15 +71,15 @@ constexpr int kUnroll2 = 8;
 //   columns and reads them with one vector load per gathered row segment.  A
 //   row's neighbour list is fetched 64 entries at a time with one coalesced load
 //   and broadcast lane by lane (readlane), so gathers never wait on index loads.
-//   Set a: Za[i,:] = rsa[i] * sum_e wa[e] S[col[e],:]          (wa/rsa may be null = 1)
-//   Set b: Zb[i,:] = sum_e csb[col[e]] S[col[e],:]            (only when TWO)
+//   Set 0: Z[i,:] = rsa[i] * sum_e wa[e] S[col[e],:]           (wa/rsa may be null = 1)
+//   Set 1: Z[i,:] = sum_e csb[col[e]] S[col[e],:]             (only when TWO)
 template <typename TS, bool TWO, int VW, int RW>
 __global__ __launch_bounds__(64 * 64 / RW) void k_stage1(const int64_t *__restrict__ rowptr,
                                                 const int32_t *__restrict__ col,
                                                 const float *__restrict__ wa, const float *__restrict__ rsa,
                                                 const float *__restrict__ csb,
                                                 const TS *__restrict__ S, int32_t n2, int32_t row0,
-                                                int32_t nrows, float *__restrict__ Za, float *__restrict__ Zb) {
+                                                int32_t nrows, float *__restrict__ Z) {
   const int lane = threadIdx.x & 63;
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int blk = blockIdx.x;
@@ -151,7 +154,6 @@ __global__ __launch_bounds__(64 * 64 / RW) void k_stage1(const int64_t *__restri
   const int64_t base = static_cast<int64_t>(blk) * n2;
 #pragma unroll
   for (int set = 0; set < (TWO ? 2 : 1); ++set) {
-    (void)Zb;
 #pragma unroll
     for (int turn = 0; turn < 64 / LP; ++turn) {
       __syncthreads();
@@ -168,7 +170,7 @@ __global__ __launch_bounds__(64 * 64 / RW) void k_stage1(const int64_t *__restri
         const int cl = q / (kZtRows / 4), part = q % (kZtRows / 4);
         if (c0 + cl < n2) {
           const float4 val = *reinterpret_cast<const float4 *>(&lds[cl * LS + part * 4]);
-          *reinterpret_cast<float4 *>(Za + ((base + c0 + cl) * NSET + set) * kZtRows + part * 4) = val;
+          *reinterpret_cast<float4 *>(Z + ((base + c0 + cl) * NSET + set) * kZtRows + part * 4) = val;
         }
       }
     }
@@ -193,16 +195,16 @@ __device__ inline double log_accurate(float x) {
 //   grid.x = 64-column output tile, grid.y = row block; 8 waves, wave w owns
 //   output columns j0+8w..j0+8w+7, lane = row of the block.
 //   COST:  C[i,j] <- C_node + le*E - ln*log(P+delta) + la*C_anc + kp*(C_prev - a_j - b_i)
-//          with E = sum_e w2a[e] Za[:,col e], P = sum_e cs2b[col e] Zb[:,col e]
+//          with E = sum_e w2a[e] Z[set 0][:,col e], P = sum_e cs2b[col e] Z[set 1][:,col e]
 //          (E, P accumulated in FP64; the tile of results is kept in FP64 until the
 //          epilogue rounds the assembled cost once)
-//   PLAIN: out[i,j] = rs[j] * sum_e Za[:,col e]
+//   PLAIN: out[i,j] = rs[j] * sum_e Z[:,col e]
 template <bool COST>
 __global__ __launch_bounds__(512) void k_stage2(const int64_t *__restrict__ rowptr,
                                                 const int32_t *__restrict__ col,
                                                 const float *__restrict__ w2a, const float *__restrict__ cs2b,
-                                                const float *__restrict__ rs, const float *__restrict__ Za,
-                                                const float *__restrict__ Zb, int32_t n2, int32_t row0,
+                                                const float *__restrict__ rs, const float *__restrict__ Z,
+                                                int32_t n2, int32_t row0,
                                                 int32_t nrows, const float *__restrict__ C_node,
                                                 const int32_t *__restrict__ partner,
                                                 const double *__restrict__ a, const double *__restrict__ b,
@@ -215,8 +217,7 @@ __global__ __launch_bounds__(512) void k_stage2(const int64_t *__restrict__ rowp
   const int blk = blockIdx.y;
   // both value sets of column l of the block sit next to each other (512 bytes)
   constexpr int NSET = COST ? 2 : 1;
-  (void)Zb;
-  const float *za = Za + static_cast<int64_t>(blk) * n2 * (kZtRows * NSET) + lane;
+  const float *za = Z + static_cast<int64_t>(blk) * n2 * (kZtRows * NSET) + lane;
   for (int jj = 0; jj < 8; ++jj) {
     const int j = j0 + w * 8 + jj;
     double E = 0.0, P = 0.0;
@@ -301,10 +302,7 @@ __global__ __launch_bounds__(512) void k_stage2(const int64_t *__restrict__ rowp
 template <typename TS>
 static int cost_chunks(const CostArgs &c, int32_t chunk_rows, void *zt, hipStream_t s, KTimer *tm) {
   const int32_t n1 = c.A1->n, n2 = c.A2->n;
-  const size_t nblk_max = (static_cast<size_t>(chunk_rows) + kZtRows - 1) / kZtRows;
-  float *Za = static_cast<float *>(zt);
-  float *Zb = reinterpret_cast<float *>(static_cast<char *>(zt) +
-                                        align_up(nblk_max * kZtRows * static_cast<size_t>(n2) * sizeof(float), 256));
+  float *Z = static_cast<float *>(zt);
   CostCoef cf;
   cf.le = c.lambda_e;
   cf.ln = c.lambda_n;
@@ -323,14 +321,14 @@ static int cost_chunks(const CostArgs &c, int32_t chunk_rows, void *zt, hipStrea
       FA_TIMED(tm, KK_STAGE1, s,
                FA_LAUNCH((k_stage1<TS, true, VW, RW>), dim3(nblk, ceil_div(n2, 64 * VW)), dim3(64 * 64 / RW), 0, s,
                          c.A1->rowptr, c.A1->colidx, c.w1, nullptr, c.inv1, static_cast<const TS *>(c.S), n2, r0, nr,
-                         Za, Zb));
+                         Z));
     else
       FA_TIMED(tm, KK_STAGE1, s,
                FA_LAUNCH((k_stage1<TS, true, 1, 8>), dim3(nblk, ceil_div(n2, 64)), dim3(512), 0, s, c.A1->rowptr,
-                         c.A1->colidx, c.w1, nullptr, c.inv1, static_cast<const TS *>(c.S), n2, r0, nr, Za, Zb));
+                         c.A1->colidx, c.w1, nullptr, c.inv1, static_cast<const TS *>(c.S), n2, r0, nr, Z));
     FA_TIMED(tm, KK_STAGE2, s,
              FA_LAUNCH((k_stage2<true>), dim3(ceil_div(n2, 64), nblk), dim3(512), 0, s, c.A2->rowptr,
-                       c.A2->colidx, c.w2, c.inv2, nullptr, Za, Zb, n2, r0, nr, c.C_node, c.partner, c.a, c.b, cf,
+                       c.A2->colidx, c.w2, c.inv2, nullptr, Z, n2, r0, nr, c.C_node, c.partner, c.a, c.b, cf,
                        c.C, c.Ct, n1));
   }
   return FA_OK;
@@ -357,12 +355,12 @@ int run_propagate(const fa_csr *A1, const float *inv1, const fa_csr *A2, const f
       const int nblk = ceil_div(nr, kZtRows);
       if (n2 % 2 == 0)
         FA_LAUNCH((k_stage1<float, false, 2, 8>), dim3(nblk, ceil_div(n2, 128)), dim3(512), 0, s, A1->rowptr,
-                  A1->colidx, nullptr, inv1, nullptr, src, n2, r0, nr, Z, nullptr);
+                  A1->colidx, nullptr, inv1, nullptr, src, n2, r0, nr, Z);
       else
         FA_LAUNCH((k_stage1<float, false, 1, 8>), dim3(nblk, ceil_div(n2, 64)), dim3(512), 0, s, A1->rowptr,
-                  A1->colidx, nullptr, inv1, nullptr, src, n2, r0, nr, Z, nullptr);
+                  A1->colidx, nullptr, inv1, nullptr, src, n2, r0, nr, Z);
       FA_LAUNCH((k_stage2<false>), dim3(ceil_div(n2, 64), nblk), dim3(512), 0, s, A2->rowptr,
-                A2->colidx, nullptr, nullptr, inv2, Z, nullptr, n2, r0, nr, nullptr, nullptr, nullptr,
+                A2->colidx, nullptr, nullptr, inv2, Z, n2, r0, nr, nullptr, nullptr, nullptr,
                 nullptr, cf, dst, nullptr, n1);
     }
     float *t = src;
