@@ -102,13 +102,6 @@ __host__ __device__ inline uint16_t f32_to_bf16(float f) {
 }
 
 template <typename T>
-__device__ inline float load_as_f32(const T *p, int64_t i);
-template <>
-__device__ inline float load_as_f32<float>(const float *p, int64_t i) { return p[i]; }
-template <>
-__device__ inline float load_as_f32<uint16_t>(const uint16_t *p, int64_t i) { return bf16_to_f32(p[i]); }
-
-template <typename T>
 __device__ inline void store_from_f32(T *p, int64_t i, float v);
 template <>
 __device__ inline void store_from_f32<float>(float *p, int64_t i, float v) { p[i] = v; }
@@ -129,11 +122,6 @@ __device__ inline void st_stream(uint16_t *p, float v) { __builtin_nontemporal_s
 
 // ---------------------------------------------------------------- reductions
 
-__device__ inline float wave_max(float v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
-  return v;
-}
 __device__ inline float wave_sum(float v) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
@@ -207,7 +195,6 @@ struct KTimer {
     }
     used = 0;
   }
-  bool nearly_full() const { return used + 16 > created; }
 };
 #define FA_TIMED(tm, kk, s, launch)                                                 \
   do {                                                                              \
