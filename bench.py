@@ -90,7 +90,7 @@ def measured_traffic(kernel, workload):
     return k.get("bytes_per_launch")
 
 
-def algorithmic_bytes(kind, n1, n2, nnz1, nnz2, chunk, sbytes, zbytes, transposed=True):
+def algorithmic_bytes(kind, n1, n2, nnz1, nnz2, chunk, sbytes, zpair, transposed=True):
     """Compulsory HBM bytes per launch of each kernel class (see the design notes)."""
     N = n1 * n2
     if kind in ("lse_col_partial", "lse_row", "lse_col_t"):
@@ -98,10 +98,10 @@ def algorithmic_bytes(kind, n1, n2, nnz1, nnz2, chunk, sbytes, zbytes, transpose
     if kind == "lse_col_merge":
         return 8 * n2 * 3
     if kind == "cost_stage1":
-        return sbytes * n1 * n2 + 2 * zbytes * chunk * n2   # S read once + both Z sets written (one chunk)
+        return sbytes * n1 * n2 + zpair * chunk * n2   # S read once + both Z sets written (one chunk)
     if kind == "cost_stage2":
         # Z read + C_node, C_prev read + C written (+ C^T written for the transposed column pass)
-        return 2 * zbytes * chunk * n2 + 12 * chunk * n2 + (4 * chunk * n2 if transposed else 0)
+        return zpair * chunk * n2 + 12 * chunk * n2 + (4 * chunk * n2 if transposed else 0)
     if kind == "plan":
         return (4 + sbytes) * N
     if kind == "featsim":
@@ -191,14 +191,16 @@ def main():
                    phase_ms=dict(phase1=st.phase_ms[0], cost=st.phase_ms[1], sinkhorn=st.phase_ms[2],
                                  plan=st.phase_ms[3]),
                    kernels={})
-        chunk = n_chunk(pair.n1, pair.n2, 4)  # the SpMM intermediate is FP32 in both forms
+        chunk = n_chunk(pair.n1, pair.n2, 4)  # chunk rows are sized for an FP32 intermediate in both forms
         chunk = pair.n1 / math.ceil(pair.n1 / chunk)  # mean rows per stage launch (the last chunk is short)
         for k, name in enumerate(KERNELS):
             calls = int(st.kernel_calls[k])
             if calls == 0:
                 continue
             avg_ms = st.kernel_ms[k] / calls
-            by = algorithmic_bytes(name, pair.n1, pair.n2, inp.A1.nnz, inp.A2.nnz, chunk, sb, 4, bool(p.transpose_cost))
+            # bytes of one Z entry over both value sets: FP32 N-set + E-set in the form's plan type
+            by = algorithmic_bytes(name, pair.n1, pair.n2, inp.A1.nnz, inp.A2.nnz, chunk, sb, 4 + sb,
+                                   bool(p.transpose_cost))
             out["kernels"][name] = dict(calls=calls, total_ms=st.kernel_ms[k], avg_ms=avg_ms,
                                         algorithmic_bytes=by, gbps=by / (avg_ms * 1e-3) / 1e9)
             if name == "featsim":

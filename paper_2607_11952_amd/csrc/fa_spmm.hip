@@ -10,10 +10,11 @@
 // Both stages read contiguous multi-hundred-byte segments: stage 1 writes Z in a
 // block-transposed layout Zt[block][l][set][r] (64 rows r of a row block stored
 // contiguously per column l, the two value sets side by side), so stage 2's
-// gather of column l of a row block is one 512-byte piece.  The intermediate is
-// FP32 in both precision forms: the BF16 form halves the reads of S, and an FP32
-// intermediate keeps E and P accurate (both stages are bound by gather traffic
-// behind L2, stage 2 accumulates in FP64).  Neighbour lists are uniform per
+// gather of column l of a row block is one 512-byte piece.  The N-set is FP32 in
+// both precision forms (log P needs it near P = 0); the BF16 form stores the
+// E-set in BF16 (a 384-byte piece), which cuts stage 2's gather traffic, the
+// fabric behind L2 that bounds it, by a quarter at a relative error of 2^-9 per
+// entry of Z_e (stage 2 accumulates in FP64).  Neighbour lists are uniform per
 // wavefront (one output row or column per wave), fetched 64 at a time with one
 // coalesced load and broadcast lane by lane, so no lane diverges on the power-law
 // degrees.  With a C^T buffer, stage 2 also writes the transposed cost for the
@@ -60,6 +61,23 @@ struct VLoad<uint16_t, 2> {
 __device__ inline int bcast_i(int v, int u) { return __builtin_amdgcn_readlane(v, u); }
 __device__ inline float bcast_f(float v, int u) { return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), u)); }
 
+// Record of one (row block, column) in Zt, in floats: the 64 rows of each value
+// set.  Both sets FP32: [E-set | N-set], 512 bytes.  With ZEB (the BF16 form) the
+// E-set is stored in BF16 after the FP32 N-set: [N-set 256 B | E-set 128 B].
+// One set (propagation): 64 floats.
+template <bool TWO, bool ZEB>
+__host__ __device__ constexpr int zt_record() {
+  return TWO ? (ZEB ? 96 : 128) : 64;
+}
+// Offset in floats of a set's rows inside the record (set 0 = E-set, set 1 = N-set).
+template <bool TWO, bool ZEB>
+__device__ constexpr int zt_offset(int set) {
+  return !TWO ? 0 : (ZEB ? (set == 0 ? 64 : 0) : set * 64);
+}
+__device__ inline uint32_t pack_bf16(float x, float y) {
+  return static_cast<uint32_t>(f32_to_bf16(x)) | (static_cast<uint32_t>(f32_to_bf16(y)) << 16);
+}
+
 // Gathers kept in flight per wave: stage 1 (row segments of S), stage 2 (Zt
 // column segments, per value set).  Both divide the 64-entry neighbour chunks.
 constexpr int kUnroll1 = 8;
@@ -73,7 +91,7 @@ constexpr int kUnroll2 = 8;
 //   and broadcast lane by lane (readlane), so gathers never wait on index loads.
 //   Set 0: Z[i,:] = rsa[i] * sum_e wa[e] S[col[e],:]           (wa/rsa may be null = 1)
 //   Set 1: Z[i,:] = sum_e csb[col[e]] S[col[e],:]             (only when TWO)
-template <typename TS, bool TWO, int VW, int RW>
+template <typename TS, bool TWO, int VW, int RW, bool ZEB>
 __global__ __launch_bounds__(64 * 64 / RW) void k_stage1(const int64_t *__restrict__ rowptr,
                                                 const int32_t *__restrict__ col,
                                                 const float *__restrict__ wa, const float *__restrict__ rsa,
@@ -150,7 +168,7 @@ __global__ __launch_bounds__(64 * 64 / RW) void k_stage1(const int64_t *__restri
   constexpr int LS = kZtRows + 4;                   // padded column stride keeps float4 alignment
   __shared__ float lds[NL * LS];
   const int ct = blockIdx.y * (64 * VW);
-  constexpr int NSET = TWO ? 2 : 1;  // the value sets of a column are interleaved: [block][l][set][r]
+  constexpr int REC = zt_record<TWO, ZEB>();  // floats per (block, column) record
   const int64_t base = static_cast<int64_t>(blk) * n2;
 #pragma unroll
   for (int set = 0; set < (TWO ? 2 : 1); ++set) {
@@ -166,11 +184,25 @@ __global__ __launch_bounds__(64 * 64 / RW) void k_stage1(const int64_t *__restri
       }
       __syncthreads();
       const int c0 = ct + turn * NL;
-      for (int q = threadIdx.x; q < NL * (kZtRows / 4); q += blockDim.x) {
-        const int cl = q / (kZtRows / 4), part = q % (kZtRows / 4);
-        if (c0 + cl < n2) {
-          const float4 val = *reinterpret_cast<const float4 *>(&lds[cl * LS + part * 4]);
-          *reinterpret_cast<float4 *>(Z + ((base + c0 + cl) * NSET + set) * kZtRows + part * 4) = val;
+      if (ZEB && set == 0) {
+        // the E-set in BF16: eight rows per 16-byte piece, after the FP32 N-set
+        for (int q = threadIdx.x; q < NL * (kZtRows / 8); q += blockDim.x) {
+          const int cl = q / (kZtRows / 8), part = q % (kZtRows / 8);
+          if (c0 + cl < n2) {
+            const float4 lo = *reinterpret_cast<const float4 *>(&lds[cl * LS + part * 8]);
+            const float4 hi = *reinterpret_cast<const float4 *>(&lds[cl * LS + part * 8 + 4]);
+            const uint4 pk = make_uint4(pack_bf16(lo.x, lo.y), pack_bf16(lo.z, lo.w), pack_bf16(hi.x, hi.y),
+                                        pack_bf16(hi.z, hi.w));
+            *reinterpret_cast<uint4 *>(Z + (base + c0 + cl) * REC + zt_offset<TWO, ZEB>(0) + part * 4) = pk;
+          }
+        }
+      } else {
+        for (int q = threadIdx.x; q < NL * (kZtRows / 4); q += blockDim.x) {
+          const int cl = q / (kZtRows / 4), part = q % (kZtRows / 4);
+          if (c0 + cl < n2) {
+            const float4 val = *reinterpret_cast<const float4 *>(&lds[cl * LS + part * 4]);
+            *reinterpret_cast<float4 *>(Z + (base + c0 + cl) * REC + zt_offset<TWO, ZEB>(set) + part * 4) = val;
+          }
         }
       }
     }
@@ -199,7 +231,7 @@ __device__ inline double log_accurate(float x) {
 //          (E, P accumulated in FP64; the tile of results is kept in FP64 until the
 //          epilogue rounds the assembled cost once)
 //   PLAIN: out[i,j] = rs[j] * sum_e Z[:,col e]
-template <bool COST>
+template <bool COST, bool ZEB>
 __global__ __launch_bounds__(512) void k_stage2(const int64_t *__restrict__ rowptr,
                                                 const int32_t *__restrict__ col,
                                                 const float *__restrict__ w2a, const float *__restrict__ cs2b,
@@ -215,9 +247,9 @@ __global__ __launch_bounds__(512) void k_stage2(const int64_t *__restrict__ rowp
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int j0 = blockIdx.x * 64;
   const int blk = blockIdx.y;
-  // both value sets of column l of the block sit next to each other (512 bytes)
-  constexpr int NSET = COST ? 2 : 1;
-  const float *za = Z + static_cast<int64_t>(blk) * n2 * (kZtRows * NSET) + lane;
+  // both value sets of column l of the block sit in one record (384 or 512 bytes)
+  constexpr int REC = zt_record<COST, ZEB>();
+  const float *zr = Z + static_cast<int64_t>(blk) * n2 * REC;
   for (int jj = 0; jj < 8; ++jj) {
     const int j = j0 + w * 8 + jj;
     double E = 0.0, P = 0.0;
@@ -238,9 +270,12 @@ __global__ __launch_bounds__(512) void k_stage2(const int64_t *__restrict__ rowp
           float x[kUnroll2], y[kUnroll2];
 #pragma unroll
           for (int t = 0; t < kUnroll2; ++t) {
-            const int64_t l = bcast_i(my_l, u + t);
-            x[t] = za[l * (kZtRows * NSET)];
-            if (COST) y[t] = za[l * (kZtRows * NSET) + kZtRows];
+            const float *rec = zr + static_cast<int64_t>(bcast_i(my_l, u + t)) * REC;
+            if (ZEB)
+              x[t] = bf16_to_f32(reinterpret_cast<const uint16_t *>(rec + zt_offset<COST, ZEB>(0))[lane]);
+            else
+              x[t] = rec[zt_offset<COST, ZEB>(0) + lane];
+            if (COST) y[t] = rec[zt_offset<COST, ZEB>(1) + lane];
           }
 #pragma unroll
           for (int t = 0; t < kUnroll2; ++t) {
@@ -317,17 +352,18 @@ static int cost_chunks(const CostArgs &c, int32_t chunk_rows, void *zt, hipStrea
     // two columns per lane (8-byte FP32 or 4-byte BF16 loads), eight rows per wave:
     // 32 accumulators and eight gathers in flight per wave at full occupancy
     constexpr int VW = 2, RW = 8;
+    constexpr bool ZEB = sizeof(TS) == 2;  // the BF16 form keeps the E-set of the intermediate in BF16
     if (n2 % VW == 0)
       FA_TIMED(tm, KK_STAGE1, s,
-               FA_LAUNCH((k_stage1<TS, true, VW, RW>), dim3(nblk, ceil_div(n2, 64 * VW)), dim3(64 * 64 / RW), 0, s,
+               FA_LAUNCH((k_stage1<TS, true, VW, RW, ZEB>), dim3(nblk, ceil_div(n2, 64 * VW)), dim3(64 * 64 / RW), 0, s,
                          c.A1->rowptr, c.A1->colidx, c.w1, nullptr, c.inv1, static_cast<const TS *>(c.S), n2, r0, nr,
                          Z));
     else
       FA_TIMED(tm, KK_STAGE1, s,
-               FA_LAUNCH((k_stage1<TS, true, 1, 8>), dim3(nblk, ceil_div(n2, 64)), dim3(512), 0, s, c.A1->rowptr,
+               FA_LAUNCH((k_stage1<TS, true, 1, 8, ZEB>), dim3(nblk, ceil_div(n2, 64)), dim3(512), 0, s, c.A1->rowptr,
                          c.A1->colidx, c.w1, nullptr, c.inv1, static_cast<const TS *>(c.S), n2, r0, nr, Z));
     FA_TIMED(tm, KK_STAGE2, s,
-             FA_LAUNCH((k_stage2<true>), dim3(ceil_div(n2, 64), nblk), dim3(512), 0, s, c.A2->rowptr,
+             FA_LAUNCH((k_stage2<true, ZEB>), dim3(ceil_div(n2, 64), nblk), dim3(512), 0, s, c.A2->rowptr,
                        c.A2->colidx, c.w2, c.inv2, nullptr, Z, n2, r0, nr, c.C_node, c.partner, c.a, c.b, cf,
                        c.C, c.Ct, n1));
   }
@@ -354,12 +390,12 @@ int run_propagate(const fa_csr *A1, const float *inv1, const fa_csr *A2, const f
       const int32_t nr = n1 - r0 < chunk_rows ? n1 - r0 : chunk_rows;
       const int nblk = ceil_div(nr, kZtRows);
       if (n2 % 2 == 0)
-        FA_LAUNCH((k_stage1<float, false, 2, 8>), dim3(nblk, ceil_div(n2, 128)), dim3(512), 0, s, A1->rowptr,
+        FA_LAUNCH((k_stage1<float, false, 2, 8, false>), dim3(nblk, ceil_div(n2, 128)), dim3(512), 0, s, A1->rowptr,
                   A1->colidx, nullptr, inv1, nullptr, src, n2, r0, nr, Z);
       else
-        FA_LAUNCH((k_stage1<float, false, 1, 8>), dim3(nblk, ceil_div(n2, 64)), dim3(512), 0, s, A1->rowptr,
+        FA_LAUNCH((k_stage1<float, false, 1, 8, false>), dim3(nblk, ceil_div(n2, 64)), dim3(512), 0, s, A1->rowptr,
                   A1->colidx, nullptr, inv1, nullptr, src, n2, r0, nr, Z);
-      FA_LAUNCH((k_stage2<false>), dim3(ceil_div(n2, 64), nblk), dim3(512), 0, s, A2->rowptr,
+      FA_LAUNCH((k_stage2<false, false>), dim3(ceil_div(n2, 64), nblk), dim3(512), 0, s, A2->rowptr,
                 A2->colidx, nullptr, nullptr, inv2, Z, n2, r0, nr, nullptr, nullptr, nullptr,
                 nullptr, cf, dst, nullptr, n1);
     }

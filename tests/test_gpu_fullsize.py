@@ -142,7 +142,9 @@ def test_fullsize_phase1_cost_sinkhorn_plan(setup, form):
                                  1.0 / deg2[ci2[rp2[j]:rp2[j + 1]]], cvals[q], (int(i), int(j)) in anchored, logS, po))
     want = np.array(want)
     err = np.abs(got - want)
-    assert np.all(err <= 2e-6 * np.maximum(1.0, np.abs(want))), (err.max(), want[np.argmax(err)])
+    # the BF16 form stores the E-set of the SpMM intermediate in BF16: |dE| <= E 2^-9 (x2 allowed)
+    e_tol = le * np.array(E_s) * 2.0 ** -8 if form == "bf16" else 0.0
+    assert np.all(err <= 2e-6 * np.maximum(1.0, np.abs(want)) + e_tol), (err.max(), want[np.argmax(err)])
     log(f"cost rebuild: max abs err {err.max():.2e} (|C| up to {np.abs(want).max():.1f})")
     del S, Cn
     torch.cuda.empty_cache()

@@ -237,10 +237,11 @@ def test_cost_per_term(api, case, terms, sdt):
                        dev["C_node"], dev["partner"], dev["a"], dev["b"], cp, dev["Cprev"]))
     tol = 2e-6 * np.abs(want).max() + 1e-5
     if sdt == "bf16":
-        # the oracle sees the BF16 plan itself; the FP32 intermediates add FP32
-        # rounding only.  Allowed: the BF16 form's stated bound with a factor 2,
-        # |dE| <= le*Emax*2^-8, |dlog P| <= 2^-8
-        tol += lam[0] * Emax * 2.0 ** -8 + lam[1] * 2.0 ** -8
+        # the oracle sees the BF16 plan itself; the BF16 form also stores the E-set
+        # of the intermediate in BF16 (relative 2^-9 per entry, sums of non-negative
+        # terms), the N-set stays FP32.  Allowed: twice the stated bound,
+        # |dE| <= le*Emax*2^-7, |dlog P| <= 2^-8
+        tol += lam[0] * Emax * 2.0 ** -7 + lam[1] * 2.0 ** -8
     err = np.abs(got - want).max()
     assert err <= tol, (terms, sdt, err, tol)
     if terms == "all":
