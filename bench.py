@@ -27,7 +27,8 @@ sys.path.insert(0, ROOT)
 
 METRIC = "align time (s) + SpMM HBM GB/s at n=120k: plain FP32 vs BF16+warm start @1e-6"
 HBM_PEAK_GBS = 8000.0
-KERNELS = ["lse_col_partial", "lse_col_merge", "lse_row", "cost_stage1", "cost_stage2", "plan", "featsim", "lse_col_t"]
+KERNELS = ["lse_col_partial", "lse_col_merge", "lse_row", "cost_stage1", "cost_stage2", "plan", "featsim", "lse_col_t",
+           "transpose", "topk"]
 MFMA_PEAK_TFLOPS = {"bf16": 2500.0, "f32": 157.3}   # dense matrix-core peaks of the part
 
 
@@ -48,6 +49,8 @@ def parse():
     ap.add_argument("--cold", action="store_true", help="headline form without the learned warm start")
     ap.add_argument("--carry", action="store_true",
                     help="headline form starts every later solve from the previous solve's duals")
+    ap.add_argument("--plan-in-ct", action="store_true",
+                    help="keep the working plan in the C^T buffer: no n1 x n2 plan buffer, top-10 lists out")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one 4 GiB device-to-device copy first (reference for HBM byte counters)")
     return ap.parse_args()
@@ -59,7 +62,8 @@ TRAFFIC = os.path.join(ROOT, "profiles", "traffic.json")
 # Kernel class -> the source file that defines it (with the shared headers).
 KERNEL_SOURCES = {"lse_col_partial": "fa_sinkhorn.hip", "lse_col_merge": "fa_sinkhorn.hip", "lse_row": "fa_sinkhorn.hip",
                   "lse_col_t": "fa_sinkhorn.hip",
-                  "plan": "fa_sinkhorn.hip", "cost_stage1": "fa_spmm.hip", "cost_stage2": "fa_spmm.hip"}
+                  "plan": "fa_sinkhorn.hip", "cost_stage1": "fa_spmm.hip", "cost_stage2": "fa_spmm.hip",
+                  "transpose": "fa_topk.hip", "topk": "fa_topk.hip"}
 
 
 def source_digest(kernel=None):
@@ -106,6 +110,10 @@ def algorithmic_bytes(kind, n1, n2, nnz1, nnz2, chunk, sbytes, zpair, transposed
         return (4 + sbytes) * N
     if kind == "featsim":
         return 4 * N          # C_node written once (operands are a few hundred MB)
+    if kind == "transpose":
+        return 8 * N          # C read, C^T written
+    if kind == "topk":
+        return 4 * N + 8 * (n1 + n2)
     return 0
 
 
@@ -147,7 +155,9 @@ def main():
     mlp = None
     if not args.cold:
         mlp = warm.load_weights(dev)
-    common = dict(eps=cfg.eps, outer_iters=T, inner_iters=cfg.inner_iters, tol=1e-6, check_every=1, profile=1)
+    common = dict(eps=cfg.eps, outer_iters=T, inner_iters=cfg.inner_iters, tol=1e-6, check_every=1, profile=1,
+                  plan_in_ct=args.plan_in_ct)
+    lean = dict(topk=10, dense_plan=False) if args.plan_in_ct else {}
     p_head = api.params(plan_dtype="bf16", feat_dtype="bf16", warm_start=mlp is not None,
                         carry_duals=args.carry, **common)
     p_plain = api.params(plan_dtype="f32", feat_dtype="f32", warm_start=False, **common)
@@ -212,8 +222,9 @@ def main():
         return out
 
     # ---------------- headline form: warm-up steps, then K timed steps
-    al = api.Aligner(inp, p_head, mlp, test_truth)
-    log(f"[bench] headline form: workspace {al.ws_bytes / 2**30:.1f} GiB, plan {al.S.numel() * al.S.element_size() / 2**30:.1f} GiB")
+    al = api.Aligner(inp, p_head, mlp, test_truth, **lean)
+    plan_gib = 0.0 if al.S is None else al.S.numel() * al.S.element_size() / 2**30
+    log(f"[bench] headline form: workspace {al.ws_bytes / 2**30:.1f} GiB, plan {plan_gib:.1f} GiB")
     for w in range(args.warmup):
         timed_run(al)
         log(f"[bench] warmup {w + 1}/{args.warmup} done")
@@ -234,7 +245,7 @@ def main():
     plain = None
     agree = None
     if not args.no_plain:
-        al = api.Aligner(inp, p_plain, None, test_truth)
+        al = api.Aligner(inp, p_plain, None, test_truth, **lean)
         res, ms = timed_run(al)
         plain = summarize(res, ms, p_plain)
         plain["ranking"] = ranking(res.rank)
@@ -274,7 +285,8 @@ def main():
                                      f"noise={cfg.noise:g} d={pair.X1.shape[1]} anchors={len(pair.anchors)} "
                                      f"eps={cfg.eps:g} outer={T} inner<={cfg.inner_iters} tol=1e-6",
                             n1=pair.n1, n2=pair.n2, outer_iters=T, inner_cap=cfg.inner_iters, tol=1e-6),
-                warm_start=mlp is not None, carry_duals=args.carry, headline=head, plain_fp32=plain, argmax_agreement=agree,
+                warm_start=mlp is not None, carry_duals=args.carry, plan_in_ct=args.plan_in_ct, headline=head,
+                plain_fp32=plain, argmax_agreement=agree,
                 spmm_gbps=spmm, roofline=roofline, cpu_baseline=cpu)
     print(json.dumps(line), flush=True)
 

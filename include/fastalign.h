@@ -76,7 +76,8 @@ typedef struct {
   int32_t outer_iters;/* outer (proximal) iterations */
   int32_t inner_iters;/* cap on Sinkhorn iterations per outer iteration */
   int32_t check_every;/* evaluate the stop rule every this many iterations (>=1) */
-  int32_t plan_dtype; /* FA_F32 or FA_BF16: storage of S (SpMM intermediates stay FP32) */
+  int32_t plan_dtype; /* FA_F32 or FA_BF16: storage of S (with FA_BF16 the C1 S half of the
+                         SpMM intermediate is BF16 too; A1^T S, whose log is taken, stays FP32) */
   int32_t feat_dtype; /* FA_F32 or FA_BF16: X-hat and R operands of fa_feature_sim */
   int32_t feat_l2norm;/* 1: row-L2-normalise the attributes before the product */
   int32_t warm_start; /* 0: cold duals; 1: learned row duals for the first solve */
@@ -88,6 +89,12 @@ typedef struct {
   int32_t transpose_cost; /* 1: fa_align keeps C^T beside C (one more n1*n2 FP32 buffer in
                          the workspace) and runs the a-update on its rows; 0: column
                          strips of C (less memory, a slower a-update) */
+  int32_t plan_in_ct; /* 1 (needs transpose_cost = 1): fa_align keeps the working plan in the
+                         C^T buffer, which is free from the plan pass until the cost rebuild
+                         has read the plan; the rebuild then writes C only and one transpose
+                         pass regenerates C^T.  No n1*n2 plan buffer is needed (S_out may be
+                         NULL; the plan is handed out as top-k lists), results are identical
+                         to plan_in_ct = 0, one extra pass over C per outer iteration. */
 } fa_params;
 
 /* Run statistics returned by fa_align (host struct). */
@@ -103,9 +110,10 @@ typedef struct {
   /* with params.profile: summed device time and launch count per kernel class:
    * [0] column LSE partials, [1] column merge, [2] row LSE, [3] cost stage 1
    * (left SpMM), [4] cost stage 2 (right SpMM + fused assembly), [5] plan,
-   * [6] node similarity (MFMA GEMM), [7] column pass over C^T */
-  double kernel_ms[8];
-  int32_t kernel_calls[8];
+   * [6] node similarity (MFMA GEMM), [7] column pass over C^T, [8] transpose of C
+   * (plan_in_ct), [9] top-k plan */
+  double kernel_ms[10];
+  int32_t kernel_calls[10];
 } fa_stats;
 
 /* Thread-local message describing the last non-OK status. */
@@ -244,6 +252,22 @@ int fa_plan(const float *C, int32_t n1, int32_t n2, double eps, const double *a,
             const double *b, void *S, int32_t s_dtype, int32_t *argmax, const int32_t *truth,
             int32_t *rank, void *stream);
 
+/* Top-k plan: for every row i the k largest entries of the plan of Eq. (4),
+ * S_ij = exp((a_j + b_i - C_ij)/eps), in one pass over C and without writing S
+ * (the plan is sparse in practice, §3.3, and a row's short list of candidates is
+ * what an alignment consumer reads).
+ *   C float[n1*n2] row-major, a double[n2], b double[n1] (device, in)
+ *   1 <= k <= min(64, n2); FA_ERR_ARG otherwise
+ *   val float[n1*k], idx int32[n1*k] (device, out, row-major): row i's entries,
+ *     ordered by the FP64 exponent (a_j + b_i - C_ij)/eps as fa_plan forms it,
+ *     larger first, lower j first on equal exponents.  idx[i*k] is fa_plan's
+ *     argmax and val[i*k + q] equals fa_plan's FP32 S at (i, idx[i*k + q]) bit
+ *     for bit.  Entries whose exponent is NaN are skipped; a row left with fewer
+ *     than k comparable entries pads with idx = -1, val = 0.
+ * Asynchronous on stream; the library allocates nothing. */
+int fa_plan_topk(const float *C, int32_t n1, int32_t n2, double eps, const double *a,
+                 const double *b, int32_t k, float *val, int32_t *idx, void *stream);
+
 /* ----------------------------------------------------------------------- */
 /* End to end (Algorithm 1)                                                  */
 /* ----------------------------------------------------------------------- */
@@ -251,23 +275,28 @@ int fa_plan(const float *C, int32_t n1, int32_t n2, double eps, const double *a,
 size_t fa_align_workspace_size(int32_t n1, int32_t n2, int32_t d, int32_t nL,
                                int64_t nnz1, int64_t nnz2, const fa_params *p);
 
-/* Align G1 and G2: Phase 1 once, then p->outer_iters times Phase 2 + Phase 3.
+/* Align G1 and G2 (Algorithm 1): Phase 1 once, then p->outer_iters times Phase 2 + Phase 3.
  *   X1 float[n1*d], X2 float[n2*d] (d may be 0: no attributes)
  *   anchors int32[nL*2]: pairs (node in G1, node in G2); each node may appear
  *     in at most one pair (FA_ERR_ARG otherwise; checked on the device, this
  *     check synchronises once)
  *   mlp_weights float[fa_mlp_param_count()] or NULL; required if p->warm_start
- *   S_out [n1*n2] of p->plan_dtype (out): the final plan
+ *   S_out [n1*n2] of p->plan_dtype (out): the final plan.  Also the working plan
+ *     of the outer iterations unless p->plan_in_ct; with p->plan_in_ct it may be
+ *     NULL (then no dense plan is written at all)
  *   a_out double[n2], b_out double[n1], argmax_out int32[n1] (out)
  *   truth int32[n1] / rank_out int32[n1]: optional (both or neither), the rank of
  *     each row's true partner in the final plan, as in fa_plan
+ *   topk (0 = none, else 1..min(64, n2)), topk_val float[n1*topk], topk_idx
+ *     int32[n1*topk] (out): the final plan's top-k lists, as in fa_plan_topk
  *   stats host fa_stats (out), may be NULL
  * The call synchronises the stream once at the end to fill stats.  Returns
  * FA_WARN_NOT_CONVERGED if tol > 0 and some inner solve missed it. */
 int fa_align(const fa_csr *A1, const fa_csr *A2, const float *X1, const float *X2, int32_t d,
              const int32_t *anchors, int32_t nL, const fa_params *p, const float *mlp_weights,
              void *S_out, double *a_out, double *b_out, int32_t *argmax_out, const int32_t *truth,
-             int32_t *rank_out, fa_stats *stats, void *ws, size_t ws_bytes, void *stream);
+             int32_t *rank_out, int32_t topk, float *topk_val, int32_t *topk_idx, fa_stats *stats,
+             void *ws, size_t ws_bytes, void *stream);
 
 /* ----------------------------------------------------------------------- */
 /* Learned warm start: per-node inputs and a 3-layer MLP                     */

@@ -37,6 +37,8 @@ with their reasons in the design notes of the repository):
 * R11 CSR: undirected, symmetrised, self-loops dropped, duplicates merged,
       columns sorted; isolated nodes have an all-zero normalised row.
 * R12 argmax ties resolve to the lowest column index.
+* R16 The top-k plan lists a row's k largest plan entries, larger log S first and,
+      on equal log S, the lower column first (R12 extended to the whole list).
 * R14 (variant) With carry_duals, every inner solve after the first starts from
       the final duals of the previous one instead of zeros.  A solve run to
       convergence reaches the same optimum from any start (its duals are unique up
@@ -239,6 +241,19 @@ def lse(x: np.ndarray, axis: int) -> np.ndarray:
 def plan(C: np.ndarray, a: np.ndarray, b: np.ndarray, eps: float) -> np.ndarray:
     """S_ij = exp((a_j + b_i - C_ij)/eps), Eq. (4)."""
     return np.exp((a[None, :] + b[:, None] - C) / eps)
+
+
+def plan_topk(C: np.ndarray, a: np.ndarray, b: np.ndarray, eps: float, k: int):
+    """Per row the k largest entries of the plan of Eq. (4) and their columns (R16).
+
+    The plan is concentrated on few entries per row (§3.3, memory reduction); the
+    list is the plan restricted to them.  Returns (values [n1, k], columns [n1, k]).
+    """
+    logS = (a[None, :] + b[:, None] - C) / eps
+    n1, n2 = logS.shape
+    cols = np.broadcast_to(np.arange(n2), (n1, n2))
+    order = np.lexsort((cols, -logS), axis=1)[:, :k]   # primary: log S descending; then column
+    return np.exp(np.take_along_axis(logS, order, axis=1)), order
 
 
 def marginal_error(C, a, b, eps: float) -> float:

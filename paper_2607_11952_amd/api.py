@@ -88,7 +88,7 @@ def params(**kw) -> B.fa_params:
     for k, v in kw.items():
         if k in ("plan_dtype", "feat_dtype") and isinstance(v, str):
             v = {"f32": B.FA_F32, "bf16": B.FA_BF16}[v]
-        if k in ("feat_l2norm", "warm_start", "profile", "carry_duals", "transpose_cost"):
+        if k in ("feat_l2norm", "warm_start", "profile", "carry_duals", "transpose_cost", "plan_in_ct"):
             v = int(v)
         setattr(p, k, v)
     if "lambda_p" not in kw:
@@ -197,6 +197,16 @@ def plan(Cm: torch.Tensor, eps: float, a: torch.Tensor, b: torch.Tensor, dtype=t
     return out if len(out) > 1 else S
 
 
+def plan_topk(Cm: torch.Tensor, eps: float, a: torch.Tensor, b: torch.Tensor, k: int):
+    """Per-row top-k of the plan without writing it: (values float32 [n1, k], columns int32 [n1, k])."""
+    n1, n2 = Cm.shape
+    val = torch.empty((n1, k), dtype=torch.float32, device=Cm.device)
+    idx = torch.empty((n1, k), dtype=torch.int32, device=Cm.device)
+    _lib().call("fa_plan_topk", _ptr(Cm), n1, n2, float(eps), _ptr(a), _ptr(b), int(k), _ptr(val), _ptr(idx),
+                _stream())
+    return val, idx
+
+
 # ------------------------------------------------------------------ end to end
 
 @dataclasses.dataclass
@@ -218,13 +228,15 @@ class AlignInputs:
 
 @dataclasses.dataclass
 class AlignResult:
-    S: torch.Tensor
+    S: Optional[torch.Tensor]   # None when the run kept no dense plan (plan_in_ct without one)
     a: torch.Tensor
     b: torch.Tensor
     argmax: torch.Tensor
     stats: B.fa_stats
     status: int
     rank: Optional[torch.Tensor] = None   # rank of each row's true partner (0: none), if asked for
+    topk_val: Optional[torch.Tensor] = None   # final plan's per-row top-k, if asked for
+    topk_idx: Optional[torch.Tensor] = None
 
 
 def workspace_bytes(inp: AlignInputs, p: B.fa_params) -> int:
@@ -236,20 +248,26 @@ class Aligner:
     """Holds the workspace and outputs for repeated fa_align calls on one input."""
 
     def __init__(self, inp: AlignInputs, p: B.fa_params, mlp: Optional[torch.Tensor] = None,
-                 truth: Optional[torch.Tensor] = None):
+                 truth: Optional[torch.Tensor] = None, topk: int = 0, dense_plan: bool = True):
         """truth (int32[n1] on the device, -1 = no partner) makes run() also rank each
-        row's true partner in the final plan (AlignResult.rank)."""
-        self.inp, self.p, self.mlp, self.truth = inp, p, mlp, truth
+        row's true partner in the final plan (AlignResult.rank); topk > 0 returns the
+        final plan's per-row top-k lists; dense_plan = False (needs p.plan_in_ct)
+        allocates no n1 x n2 plan at all."""
+        if not dense_plan and not p.plan_in_ct:
+            raise ValueError("dense_plan=False needs plan_in_ct=1")
+        self.inp, self.p, self.mlp, self.truth, self.topk = inp, p, mlp, truth, int(topk)
         n1, n2 = inp.A1.n, inp.A2.n
         dev = inp.X1.device
         self.ws_bytes = workspace_bytes(inp, p)
         self.ws = torch.empty(self.ws_bytes, dtype=torch.uint8, device=dev)
         sd = torch.bfloat16 if p.plan_dtype == B.FA_BF16 else torch.float32
-        self.S = torch.empty((n1, n2), dtype=sd, device=dev)
+        self.S = torch.empty((n1, n2), dtype=sd, device=dev) if dense_plan else None
         self.a = torch.empty(n2, dtype=torch.float64, device=dev)
         self.b = torch.empty(n1, dtype=torch.float64, device=dev)
         self.argmax = torch.empty(n1, dtype=torch.int32, device=dev)
         self.rank = torch.empty(n1, dtype=torch.int32, device=dev) if truth is not None else None
+        self.topk_val = torch.empty((n1, self.topk), dtype=torch.float32, device=dev) if self.topk else None
+        self.topk_idx = torch.empty((n1, self.topk), dtype=torch.int32, device=dev) if self.topk else None
 
     def run(self) -> AlignResult:
         st = B.fa_stats()
@@ -257,13 +275,14 @@ class Aligner:
         status = _lib().call("fa_align", C.byref(inp.A1.c), C.byref(inp.A2.c), _ptr(inp.X1), _ptr(inp.X2),
                              int(inp.X1.shape[1]), _ptr(inp.anchors), int(inp.anchors.shape[0]), C.byref(self.p),
                              _ptr(self.mlp), _ptr(self.S), _ptr(self.a), _ptr(self.b), _ptr(self.argmax),
-                             _ptr(self.truth), _ptr(self.rank), C.byref(st), _ptr(self.ws), self.ws_bytes, _stream())
-        return AlignResult(self.S, self.a, self.b, self.argmax, st, status, self.rank)
+                             _ptr(self.truth), _ptr(self.rank), self.topk, _ptr(self.topk_val), _ptr(self.topk_idx),
+                             C.byref(st), _ptr(self.ws), self.ws_bytes, _stream())
+        return AlignResult(self.S, self.a, self.b, self.argmax, st, status, self.rank, self.topk_val, self.topk_idx)
 
 
 def align(inp: AlignInputs, p: B.fa_params, mlp: Optional[torch.Tensor] = None,
-          truth: Optional[torch.Tensor] = None) -> AlignResult:
-    return Aligner(inp, p, mlp, truth).run()
+          truth: Optional[torch.Tensor] = None, topk: int = 0, dense_plan: bool = True) -> AlignResult:
+    return Aligner(inp, p, mlp, truth, topk, dense_plan).run()
 
 
 # ------------------------------------------------------------------ warm start pieces

@@ -23,7 +23,7 @@ EXPORTS = [
     "fa_propagate", "fa_cost", "fa_sinkhorn_workspace_size", "fa_sinkhorn", "fa_plan",
     "fa_align_workspace_size", "fa_align", "fa_node_feature_dim", "fa_node_features_workspace_size",
     "fa_node_features", "fa_mlp_param_count", "fa_mlp_act_floats", "fa_mlp_forward",
-    "fa_mlp_backward", "fa_adam_step", "fa_stream_read",
+    "fa_mlp_backward", "fa_adam_step", "fa_stream_read", "fa_plan_topk",
 ]
 
 
@@ -42,6 +42,7 @@ class fa_params(C.Structure):
         ("profile", C.c_int32),
         ("carry_duals", C.c_int32),
         ("transpose_cost", C.c_int32),
+        ("plan_in_ct", C.c_int32),
     ]
 
 
@@ -50,7 +51,7 @@ class fa_stats(C.Structure):
         ("outer_done", C.c_int32), ("inner_total", C.c_int32), ("fell_back", C.c_int32),
         ("converged_all", C.c_int32), ("marg_err", C.c_double), ("phase_ms", C.c_double * 4),
         ("inner_iters", C.c_int32 * 64), ("inner_err", C.c_double * 64),
-        ("kernel_ms", C.c_double * 8), ("kernel_calls", C.c_int32 * 8),
+        ("kernel_ms", C.c_double * 10), ("kernel_calls", C.c_int32 * 10),
     ]
 
 
@@ -78,9 +79,10 @@ _SIGS = {
     "fa_sinkhorn_workspace_size": (_SZ, [_I32, _I32]),
     "fa_sinkhorn": (C.c_int, [_P, _P, _I32, _I32, _D, _P, _P, _I32, _D, _I32, _P, _P, _P, _P, _P, _SZ, _P]),
     "fa_plan": (C.c_int, [_P, _I32, _I32, _D, _P, _P, _P, _I32, _P, _P, _P, _P]),
+    "fa_plan_topk": (C.c_int, [_P, _I32, _I32, _D, _P, _P, _I32, _P, _P, _P]),
     "fa_align_workspace_size": (_SZ, [_I32, _I32, _I32, _I32, _I64, _I64, C.POINTER(fa_params)]),
     "fa_align": (C.c_int, [C.POINTER(fa_csr), C.POINTER(fa_csr), _P, _P, _I32, _P, _I32, C.POINTER(fa_params),
-                           _P, _P, _P, _P, _P, _P, _P, C.POINTER(fa_stats), _P, _SZ, _P]),
+                           _P, _P, _P, _P, _P, _P, _P, _I32, _P, _P, C.POINTER(fa_stats), _P, _SZ, _P]),
     "fa_node_feature_dim": (_I32, []),
     "fa_node_features_workspace_size": (_SZ, [_I32]),
     "fa_node_features": (C.c_int, [C.POINTER(fa_csr), _P, _P, _I32, _P, _P, _I32, _P, _P, _SZ, _P]),

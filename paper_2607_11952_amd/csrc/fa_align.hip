@@ -123,6 +123,7 @@ static int validate(const fa_csr *A1, const fa_csr *A2, int32_t d, int32_t nL, c
              p->plan_dtype);
   FA_REQUIRE(p->feat_dtype == FA_F32 || p->feat_dtype == FA_BF16, FA_ERR_ARG, "fa_align: feat_dtype %d",
              p->feat_dtype);
+  FA_REQUIRE(!p->plan_in_ct || p->transpose_cost, FA_ERR_ARG, "fa_align: plan_in_ct needs transpose_cost = 1");
   return FA_OK;
 }
 
@@ -139,11 +140,14 @@ extern "C" size_t fa_align_workspace_size(int32_t n1, int32_t n2, int32_t d, int
 extern "C" int fa_align(const fa_csr *A1, const fa_csr *A2, const float *X1, const float *X2, int32_t d,
                         const int32_t *anchors, int32_t nL, const fa_params *p, const float *mlp_weights, void *S_out,
                         double *a_out, double *b_out, int32_t *argmax_out, const int32_t *truth,
-                        int32_t *rank_out, fa_stats *stats, void *ws, size_t ws_bytes, void *stream) {
+                        int32_t *rank_out, int32_t topk, float *topk_val, int32_t *topk_idx, fa_stats *stats,
+                        void *ws, size_t ws_bytes, void *stream) {
   FA_TRY(validate(A1, A2, d, nL, p));
   FA_REQUIRE((truth == nullptr) == (rank_out == nullptr), FA_ERR_ARG, "fa_align: truth and rank_out go together");
   const int32_t n1 = A1->n, n2 = A2->n;
-  FA_REQUIRE(S_out && a_out && b_out && argmax_out, FA_ERR_ARG, "fa_align: null output");
+  FA_REQUIRE((S_out || p->plan_in_ct) && a_out && b_out && argmax_out, FA_ERR_ARG, "fa_align: null output");
+  FA_REQUIRE(topk == 0 || (topk >= 1 && topk <= kTopkMax && topk <= n2 && topk_val && topk_idx), FA_ERR_ARG,
+             "fa_align: topk = %d needs 1 <= topk <= min(%d, n2) and both top-k outputs", topk, kTopkMax);
   FA_REQUIRE(d == 0 || (X1 && X2), FA_ERR_ARG, "fa_align: null attributes with d = %d", d);
   FA_REQUIRE(nL == 0 || anchors, FA_ERR_ARG, "fa_align: null anchors");
   FA_REQUIRE(!p->warm_start || mlp_weights, FA_ERR_ARG, "fa_align: warm_start needs mlp_weights");
@@ -156,6 +160,12 @@ extern "C" int fa_align(const fa_csr *A1, const fa_csr *A2, const float *X1, con
   carve_align(cv, n1, n2, d, nL, A1->nnz, A2->nnz, p, L, &B);
   FA_TRY(carve_sinkhorn(cv, n1, n2, B.sink));
   FA_REQUIRE(cv.ok, FA_ERR_WORKSPACE, "fa_align: workspace carve failed");
+  // The working plan: the caller's S_out, or the C^T buffer (FP32 n2 x n1, at least
+  // as large as an n1 x n2 plan of either type) between the plan pass and the next
+  // cost rebuild.
+  const bool plan_in_ct = p->plan_in_ct != 0;
+  void *S_work = plan_in_ct ? static_cast<void *>(B.Ct) : S_out;
+  void *S_final = S_out ? S_out : S_work;
   const int T = p->outer_iters;
   KTimer *tm = nullptr;
   struct TmGuard {
@@ -228,7 +238,7 @@ extern "C" int fa_align(const fa_csr *A1, const fa_csr *A2, const float *X1, con
   FA_TRY(launch_fill_f64(a_out, n2, 0.0, s));
   FA_TRY(launch_fill_f64(b_out, n1, 0.0, s));
   FA_TRY(launch_fill_f32(B.C, static_cast<int64_t>(N), static_cast<float>(p->eps * log(static_cast<double>(n1) * n2)), s));
-  FA_TRY(run_plan(B.C, n1, n2, p->eps, a_out, b_out, S_out, p->plan_dtype, nullptr, nullptr, nullptr, s));
+  FA_TRY(run_plan(B.C, n1, n2, p->eps, a_out, b_out, S_work, p->plan_dtype, nullptr, nullptr, nullptr, s));
   if (p->warm_start) {
     FA_TRY(run_node_features(A1, B.inv1, X1, d, nullptr, B.nodes1, nL, B.feat, B.nf_ws, node_features_ws_bytes(n1),
                              s));
@@ -239,14 +249,15 @@ extern "C" int fa_align(const fa_csr *A1, const fa_csr *A2, const float *X1, con
   FA_HIP(hipEventElapsedTime(&f, ev[0], ev[1]));
   ms_p1 = f;
 
-  CostArgs c{A1, A2, B.w1, B.inv1, B.w2, B.inv2, S_out, p->plan_dtype, B.C_node, B.partner, a_out, b_out,
+  CostArgs c{A1, A2, B.w1, B.inv1, B.w2, B.inv2, S_work, p->plan_dtype, B.C_node, B.partner, a_out, b_out,
              p->lambda_e, p->lambda_n, p->lambda_a, p->lambda_p, p->eps, p->eps_anchor, p->delta_nbr, B.C,
-             p->transpose_cost ? B.Ct : nullptr};
+             p->transpose_cost && !plan_in_ct ? B.Ct : nullptr};
   // Events: ev[0] start of cost, ev[1] end of cost, ev[2] end of Sinkhorn, ev[3] end of plan.
   double t_cost = 0, t_sink = 0, t_plan = 0;
   for (int t = 0; t < T; ++t) {
     FA_HIP(hipEventRecord(ev[0], s));
     FA_TRY(run_cost(c, L.chunk_rows, B.zt, s, tm));
+    if (plan_in_ct) FA_TRY(run_transpose(B.C, n1, n2, B.Ct, s, tm));  // overwrites the plan just read
     FA_HIP(hipEventRecord(ev[1], s));
     if (p->warm_start && t == 0) {
       FA_TRY(warm_start_duals(mlp_weights, B.feat, n1, B.act, p->eps, B.bad + 2, b_out, s));
@@ -260,7 +271,8 @@ extern "C" int fa_align(const fa_csr *A1, const fa_csr *A2, const float *X1, con
     FA_TRY(run_sinkhorn(B.C, p->transpose_cost ? B.Ct : nullptr, n1, n2, p->eps, a_out, b_out, p->inner_iters,
                         p->tol, p->check_every, it_slot, er_slot, B.sink, s, tm));
     FA_HIP(hipEventRecord(ev[2], s));
-    FA_TRY(run_plan(B.C, n1, n2, p->eps, a_out, b_out, S_out, p->plan_dtype, t == T - 1 ? argmax_out : nullptr,
+    FA_TRY(run_plan(B.C, n1, n2, p->eps, a_out, b_out, t == T - 1 ? S_final : S_work, p->plan_dtype,
+                    t == T - 1 ? argmax_out : nullptr,
                     t == T - 1 ? truth : nullptr, t == T - 1 ? rank_out : nullptr, s,
                     tm));
     FA_HIP(hipEventRecord(ev[3], s));
@@ -276,7 +288,8 @@ extern "C" int fa_align(const fa_csr *A1, const fa_csr *A2, const float *X1, con
     t_plan += x;
     if (tm) tm->collect();
   }
-  if (T == 0) FA_TRY(run_plan(B.C, n1, n2, p->eps, a_out, b_out, S_out, p->plan_dtype, argmax_out, truth, rank_out, s));
+  if (T == 0) FA_TRY(run_plan(B.C, n1, n2, p->eps, a_out, b_out, S_final, p->plan_dtype, argmax_out, truth, rank_out, s));
+  if (topk > 0) FA_TRY(run_plan_topk(B.C, n1, n2, p->eps, a_out, b_out, topk, topk_val, topk_idx, s, tm));
   ms_cost = t_cost;
   ms_sink = t_sink;
   ms_plan = t_plan;
@@ -291,6 +304,7 @@ extern "C" int fa_align(const fa_csr *A1, const fa_csr *A2, const float *X1, con
     FA_HIP(hipMemcpyAsync(errs, B.st_err, sizeof(double) * nrec, hipMemcpyDeviceToHost, s));
   }
   FA_HIP(hipStreamSynchronize(s));
+  if (tm) tm->collect();  // launches after the last outer iteration (top-k; all of them if T = 0)
   bool all_conv = true;
   int32_t total = 0;
   for (int t = 0; t < nrec; ++t) {

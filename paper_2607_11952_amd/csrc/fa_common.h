@@ -120,6 +120,47 @@ __device__ inline f32x4 ld_stream4(const float *p) {
 __device__ inline void st_stream(float *p, float v) { __builtin_nontemporal_store(v, p); }
 __device__ inline void st_stream(uint16_t *p, float v) { __builtin_nontemporal_store(f32_to_bf16(v), p); }
 
+// V consecutive floats of a streamed row (V = 1, 4, 8).
+template <int V>
+struct Vec;
+template <>
+struct Vec<1> {
+  static __device__ inline void load(const float *p, float *o) { o[0] = ld_stream(p); }
+};
+template <>
+struct Vec<4> {
+  static __device__ inline void load(const float *p, float *o) {
+    const f32x4 t = ld_stream4(p);
+    o[0] = t.x;
+    o[1] = t.y;
+    o[2] = t.z;
+    o[3] = t.w;
+  }
+};
+
+template <>
+struct Vec<8> {
+  static __device__ inline void load(const float *p, float *o) {
+    const f32x4 t = ld_stream4(p), u = ld_stream4(p + 4);
+    o[0] = t.x;
+    o[1] = t.y;
+    o[2] = t.z;
+    o[3] = t.w;
+    o[4] = u.x;
+    o[5] = u.y;
+    o[6] = u.z;
+    o[7] = u.w;
+  }
+};
+
+// 2^y for an FP64 exponent: integer part exact (ldexp), fraction through FP32 exp2.
+__device__ inline float exp2_split(double y) {
+  if (!(y > -1000.0)) return 0.0f;
+  if (y > 200.0) return INFINITY;
+  const double fl = floor(y);
+  return ldexpf(exp2f(static_cast<float>(y - fl)), static_cast<int>(fl));
+}
+
 // ---------------------------------------------------------------- reductions
 
 __device__ inline float wave_sum(float v) {
@@ -157,7 +198,19 @@ inline int ceil_div(int64_t a, int64_t b) { return static_cast<int>((a + b - 1) 
 // Optional per-kernel timing with HIP events recorded on the launch stream around
 // individual launches.  Events come from a fixed pool; collect() must be called
 // after the stream has reached the last recorded event.
-enum KernelKind { KK_COL_PARTIAL = 0, KK_COL_MERGE, KK_ROW, KK_STAGE1, KK_STAGE2, KK_PLAN, KK_FEATSIM, KK_COL_T, KK_COUNT };
+enum KernelKind {
+  KK_COL_PARTIAL = 0,
+  KK_COL_MERGE,
+  KK_ROW,
+  KK_STAGE1,
+  KK_STAGE2,
+  KK_PLAN,
+  KK_FEATSIM,
+  KK_COL_T,
+  KK_TRANSPOSE,
+  KK_TOPK,
+  KK_COUNT
+};
 struct KTimer {
   static constexpr int kPool = 2048;
   hipEvent_t ev[kPool];

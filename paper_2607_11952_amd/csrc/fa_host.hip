@@ -49,6 +49,7 @@ extern "C" void fa_default_params(fa_params *p) {
   p->profile = 0;
   p->carry_duals = 0;
   p->transpose_cost = 1;
+  p->plan_in_ct = 0;
 }
 
 extern "C" int fa_device_check(void) {

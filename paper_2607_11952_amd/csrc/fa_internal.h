@@ -67,6 +67,13 @@ int run_plan(const float *C, int32_t n1, int32_t n2, double eps, const double *a
              int32_t sdt, int32_t *argmax, const int32_t *truth, int32_t *rank, hipStream_t s,
              KTimer *tm = nullptr);
 
+// The plan without a dense buffer of its own: per-row top-k (k <= kTopkMax) and
+// the transpose that regenerates C^T when the working plan lives in its buffer.
+constexpr int kTopkMax = 64;
+int run_plan_topk(const float *C, int32_t n1, int32_t n2, double eps, const double *a, const double *b, int32_t k,
+                  float *val, int32_t *idx, hipStream_t s, KTimer *tm = nullptr);
+int run_transpose(const float *C, int32_t n1, int32_t n2, float *Ct, hipStream_t s, KTimer *tm = nullptr);
+
 // Warm start.
 int run_node_features(const fa_csr *A, const float *inv_deg, const float *X, int32_t d, const float *proj,
                       const int32_t *anchor_nodes, int32_t nL, float *out, void *ws, size_t ws_bytes,

@@ -82,38 +82,6 @@ int carve_sinkhorn(Carver &cv, int32_t n1, int32_t n2, SinkWs &w) {
   return cv.ok ? FA_OK : FA_ERR_WORKSPACE;
 }
 
-template <int V>
-struct Vec;
-template <>
-struct Vec<1> {
-  static __device__ inline void load(const float *p, float *o) { o[0] = ld_stream(p); }
-};
-template <>
-struct Vec<4> {
-  static __device__ inline void load(const float *p, float *o) {
-    const f32x4 t = ld_stream4(p);
-    o[0] = t.x;
-    o[1] = t.y;
-    o[2] = t.z;
-    o[3] = t.w;
-  }
-};
-
-template <>
-struct Vec<8> {
-  static __device__ inline void load(const float *p, float *o) {
-    const f32x4 t = ld_stream4(p), u = ld_stream4(p + 4);
-    o[0] = t.x;
-    o[1] = t.y;
-    o[2] = t.z;
-    o[3] = t.w;
-    o[4] = u.x;
-    o[5] = u.y;
-    o[6] = u.z;
-    o[7] = u.w;
-  }
-};
-
 // Vector store of V consecutive plan entries (one 16-byte FP32 or 8-byte BF16
 // store per lane for V = 4).
 template <typename T, int V>
@@ -532,14 +500,6 @@ int run_sinkhorn(const float *C, const float *Ct, int32_t n1, int32_t n2, double
   }
   FA_LAUNCH(k_final_a, dim3(ceil_div(n2, 256)), dim3(256), 0, s, a, w.a_next, n2, ctl);
   return FA_OK;
-}
-
-// 2^y for an FP64 exponent: integer part exact (ldexp), fraction through FP32 exp2.
-__device__ inline float exp2_split(double y) {
-  if (!(y > -1000.0)) return 0.0f;
-  if (y > 200.0) return INFINITY;
-  const double fl = floor(y);
-  return ldexpf(exp2f(static_cast<float>(y - fl)), static_cast<int>(fl));
 }
 
 // Plan S = exp2((a_j + b_i - C_ij) * log2(e)/eps), optional row argmax of the FP64 exponent.

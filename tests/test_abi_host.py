@@ -78,3 +78,15 @@ def test_default_params_and_sizes(lib):
     for dt in (binding.FA_F32, binding.FA_BF16):
         assert lib.raw("fa_cost_workspace_size")(1000, 900, dt, 0) == want
     assert lib.raw("fa_cost_workspace_size")(1000, 900, binding.FA_F32, 100) == 2 * 128 * 900 * 4
+
+
+def test_plan_topk_rejects_bad_arguments_before_any_device_work(lib):
+    """k outside [1, min(64, n2)] and null outputs are refused on the host (no GPU)."""
+    from paper_2607_11952_amd import binding
+    f = lib.raw("fa_plan_topk")
+    assert f(None, 4, 8, 0.1, None, None, 0, None, None, None) == binding.FA_ERR_ARG
+    assert f(None, 4, 100, 0.1, None, None, 65, None, None, None) == binding.FA_ERR_ARG
+    assert f(None, 4, 8, 0.1, None, None, 9, None, None, None) == binding.FA_ERR_ARG
+    assert f(None, 4, 8, 0.1, None, None, 3, None, None, None) == binding.FA_ERR_ARG   # null pointers
+    assert f(None, 4, 8, -1.0, None, None, 3, None, None, None) == binding.FA_ERR_ARG
+    assert f(None, 0, 8, 0.1, None, None, 3, None, None, None) == binding.FA_OK        # no rows: nothing to do

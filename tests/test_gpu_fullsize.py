@@ -15,6 +15,7 @@ import numpy as np
 import pytest
 
 from oracle import fastalign_oracle as O
+from rank_checks import check_ranks_against_lists
 from paper_2607_11952_amd.synth import CONFIGS, make_pair
 
 pytestmark = pytest.mark.gpu
@@ -171,3 +172,57 @@ def test_fullsize_phase1_cost_sinkhorn_plan(setup, form):
         y = a_h + b_h[i] - row
         assert y[am_h[i]] >= y.max() - 1e-12 * max(1.0, abs(y.max())), (i, am_h[i], int(np.argmax(y)))
     log(f"Sinkhorn on the rebuilt cost: reported error {err_rep:.6e}, recomputed {err_ref:.6e}; argmax ok")
+
+
+BEYOND_N = 145000   # the benchmark's recipe at a size a dense plan cannot reach on a 288 GiB card
+
+
+@pytest.mark.parametrize("form", ["bf16", "f32"])
+def test_beyond_the_dense_plan_ceiling(setup, form):
+    """Past the memory ceiling of a dense plan: at n1 = n2 = 145,000 (Chung-Lu, d = 128,
+    2% anchors) the library's own workspace query plus a dense plan exceeds the card's
+    memory in both forms, while the run with the working plan in the C^T buffer fits.
+    Two outer iterations of 10 inner iterations run there without any n1 x n2 plan;
+    the top-k lists agree with the argmax and the ranks of the plan pass, are sorted,
+    hold at most the row marginal mu_i = 1/n1 (rows are exact after a b-update) and
+    start with an entry of at least mu_i / n2."""
+    import ctypes
+    import dataclasses
+    import gc
+    api = setup["api"]
+    gc.collect()
+    torch.cuda.empty_cache()
+    cfg = dataclasses.replace(CONFIGS["c5"], name="cl145k", n1=BEYOND_N)
+    pr = make_pair(cfg)
+    inp = api.AlignInputs.from_pair(pr)
+    n = pr.n1
+    kw = dict(eps=cfg.eps, outer_iters=2, inner_iters=10, plan_dtype=form, feat_dtype=form)
+    cap = torch.cuda.get_device_properties(0).total_memory
+    dense = api.workspace_bytes(inp, api.params(**kw)) + n * n * (2 if form == "bf16" else 4)
+    lean_p = api.params(plan_in_ct=1, **kw)
+    lean = api.workspace_bytes(inp, lean_p)
+    log(f"[{form}] n={n}: dense plan needs {dense / 1e9:.1f} GB, plan in C^T {lean / 1e9:.1f} GB, card {cap / 1e9:.1f} GB")
+    if not (dense > cap and lean < 0.95 * cap):
+        pytest.skip("the card's memory does not separate the two modes at this size")
+    truth = pr.truth.astype(np.int32).copy()
+    truth[pr.anchors[:, 0]] = -1
+    k = 8
+    res = api.align(inp, lean_p, truth=torch.from_numpy(truth).cuda(), topk=k, dense_plan=False)
+    torch.cuda.synchronize()
+    assert res.S is None and list(res.stats.inner_iters)[:2] == [10, 10]
+    assert torch.isfinite(res.a).all() and torch.isfinite(res.b).all()
+    val, idx = res.topk_val, res.topk_idx
+    assert torch.equal(idx[:, 0], res.argmax)
+    # sorted, and each row's mass mu_i = 1/n (exact after the b-update, up to FP32
+    # rounding) bounds the listed sum from above and the largest entry from below
+    # (entries far below the top underflow FP32 to 0 once the plan is sharp)
+    assert bool((val[:, :-1] >= val[:, 1:]).all()) and bool((val[:, -1] >= 0).all())
+    assert bool((val.double().sum(1) <= (1.0 + 1e-5) / n).all())
+    assert bool((val[:, 0].double() >= (1.0 - 1e-5) / (n * n)).all())
+    rk = res.rank.cpu().numpy()
+    rows = check_ranks_against_lists(rk, truth, val.cpu().numpy(), idx.cpu().numpy())
+    log(f"[{form}] n={n}: Hits@1 {np.mean(rk[rows] == 1):.4f}, Hits@{k} {np.mean(rk[rows] <= k):.4f} "
+        f"after 2 x 10 iterations, marginal error {res.stats.marg_err:.3e}")
+    del res, val, idx, inp
+    gc.collect()
+    torch.cuda.empty_cache()

@@ -481,3 +481,35 @@ def test_true_partner_ranks_vs_rankdata_and_closed_forms():
     rk = np.array([1, 2, 0, 10, 1, 4])
     assert O.hits_at_k(rk, 1) == 2 / 5 and O.hits_at_k(rk, 4) == 4 / 5 and O.hits_at_k(rk, 10) == 1.0
     assert math.isclose(O.mean_reciprocal_rank(rk), (1 + 0.5 + 0.1 + 1 + 0.25) / 5)
+
+
+def test_plan_topk_vs_library_sort_and_stable_brute_force():
+    """R16: the top-k lists against numpy's argmax and sort (random plans) and, where
+    plan entries tie exactly, against Python's stable sort by explicit loops (equal
+    entries keep column order, so the lower column comes first).  Descending order,
+    the tie rule and the row/column orientation each break one of these."""
+    r = rng(21)
+    n1, n2, eps = 7, 23, 0.1
+    C, a, b = r.random((n1, n2)), r.normal(size=n2), r.normal(size=n1)
+    S = O.plan(C, a, b, eps)
+    for k in (1, 5, n2):
+        val, idx = O.plan_topk(C, a, b, eps, k)
+        assert val.shape == (n1, k) and idx.shape == (n1, k)
+        assert np.array_equal(idx[:, 0], np.argmax(S, axis=1))
+        np.testing.assert_allclose(val, -np.sort(-S, axis=1)[:, :k], rtol=1e-14)
+        np.testing.assert_allclose(val, np.take_along_axis(S, idx, axis=1), rtol=1e-14)
+    # k = n2: a permutation of the columns whose values add up to the row sums; after
+    # a Sinkhorn b-update the rows carry mu_i = 1/n1 exactly (Eq. (3))
+    a2, b2, _, _ = O.sinkhorn(C, eps, 3)
+    val, idx = O.plan_topk(C, a2, b2, eps, n2)
+    assert all(sorted(row) == list(range(n2)) for row in idx)
+    np.testing.assert_allclose(val.sum(axis=1), 1.0 / n1, rtol=1e-12)
+    # exact ties: integer costs on a coarse grid, zero duals
+    Ct = r.integers(0, 4, size=(n1, n2)).astype(np.float64)
+    z2, z1 = np.zeros(n2), np.zeros(n1)
+    St = O.plan(Ct, z2, z1, 0.5)
+    for k in (3, 9, n2):
+        _, idx = O.plan_topk(Ct, z2, z1, 0.5, k)
+        for i in range(n1):
+            want = sorted(range(n2), key=lambda j: -St[i, j])[:k]   # stable: lower j first on ties
+            assert list(idx[i]) == want
