@@ -49,6 +49,10 @@ struct AlignBufs {
   void *nf_ws;
 };
 
+// Row stride of the BF16 encodings: whole 16-byte pieces, so that the similarity
+// GEMM stages them with vector loads; the zero pad adds nothing to R1 R2^T.
+static int32_t bf16_stride(int32_t nL) { return (nL + 7) / 8 * 8; }
+
 template <typename Cv>
 static void carve_align(Cv &cv, int32_t n1, int32_t n2, int32_t d, int32_t nL, int64_t nnz1, int64_t nnz2,
                         const fa_params *p, const AlignLayout &L, AlignBufs *B) {
@@ -72,13 +76,7 @@ static void carve_align(Cv &cv, int32_t n1, int32_t n2, int32_t d, int32_t nL, i
   b.nodes1 = T((int32_t *)0, nL + 1);
   b.nodes2 = T((int32_t *)0, nL + 1);
   b.bad = T((int32_t *)0, 4);
-  b.R1 = T((float *)0, static_cast<size_t>(n1) * nL);
-  b.R1t = T((float *)0, static_cast<size_t>(n1) * nL);
-  b.R2 = T((float *)0, static_cast<size_t>(n2) * nL);
-  b.R2t = T((float *)0, static_cast<size_t>(n2) * nL);
   if (bf) {
-    b.Rb1 = T((uint16_t *)0, static_cast<size_t>(n1) * nL);
-    b.Rb2 = T((uint16_t *)0, static_cast<size_t>(n2) * nL);
     b.Xh1 = T((uint16_t *)0, static_cast<size_t>(n1) * d);
     b.Xh2 = T((uint16_t *)0, static_cast<size_t>(n2) * d);
   } else {
@@ -90,6 +88,38 @@ static void carve_align(Cv &cv, int32_t n1, int32_t n2, int32_t d, int32_t nL, i
   b.C_node = T((float *)0, N);
   b.C = T((float *)0, N);
   if (p->transpose_cost) b.Ct = T((float *)0, N);
+  // Phase-1 encodings R1, R2 and their ping-pong scratch are dead once the SDDMMs and
+  // the similarity GEMM have run, before C is first written (propagation scratch or
+  // the initial fill), so they live inside C when they fit; the BF16 copies then reuse
+  // the scratch halves, dead once the encodings are built.  Otherwise they get buffers
+  // of their own.
+  const size_t r1 = align_up(static_cast<size_t>(n1) * nL * sizeof(float), 256);
+  const size_t r2 = align_up(static_cast<size_t>(n2) * nL * sizeof(float), 256);
+  const size_t s1 = static_cast<size_t>(n1) * bf16_stride(nL) * sizeof(uint16_t);
+  const size_t s2 = static_cast<size_t>(n2) * bf16_stride(nL) * sizeof(uint16_t);
+  const bool in_c = 2 * (r1 + r2) <= N * sizeof(float) && (!bf || (s1 <= r1 && s2 <= r2));
+  if (in_c) {
+    if constexpr (!std::is_same_v<Cv, Sizer>) {
+      char *c = reinterpret_cast<char *>(b.C);
+      b.R1 = reinterpret_cast<float *>(c);
+      b.R1t = reinterpret_cast<float *>(c + r1);
+      b.R2 = reinterpret_cast<float *>(c + 2 * r1);
+      b.R2t = reinterpret_cast<float *>(c + 2 * r1 + r2);
+      if (bf) {
+        b.Rb1 = reinterpret_cast<uint16_t *>(b.R1t);
+        b.Rb2 = reinterpret_cast<uint16_t *>(b.R2t);
+      }
+    }
+  } else {
+    b.R1 = T((float *)0, static_cast<size_t>(n1) * nL);
+    b.R1t = T((float *)0, static_cast<size_t>(n1) * nL);
+    b.R2 = T((float *)0, static_cast<size_t>(n2) * nL);
+    b.R2t = T((float *)0, static_cast<size_t>(n2) * nL);
+    if (bf) {
+      b.Rb1 = T((uint16_t *)0, static_cast<size_t>(n1) * bf16_stride(nL));
+      b.Rb2 = T((uint16_t *)0, static_cast<size_t>(n2) * bf16_stride(nL));
+    }
+  }
   b.zt = T((char *)0, zt_bytes(L.chunk_rows, n2));
   b.sink.pm = nullptr;
   b.st_iters = T((int32_t *)0, 64);
@@ -223,14 +253,16 @@ extern "C" int fa_align(const fa_csr *A1, const fa_csr *A2, const float *X1, con
     }
   }
   const void *R1op = B.R1, *R2op = B.R2;
+  int32_t nLop = nL;
   if (fdt == FA_BF16) {
-    FA_TRY(launch_f32_to_bf16(B.R1, static_cast<int64_t>(n1) * nL, B.Rb1, s));
-    FA_TRY(launch_f32_to_bf16(B.R2, static_cast<int64_t>(n2) * nL, B.Rb2, s));
+    nLop = bf16_stride(nL);
+    FA_TRY(launch_f32_to_bf16_rows(B.R1, n1, nL, nLop, B.Rb1, s));
+    FA_TRY(launch_f32_to_bf16_rows(B.R2, n2, nL, nLop, B.Rb2, s));
     R1op = B.Rb1;
     R2op = B.Rb2;
   }
   FA_TIMED(tm, KK_FEATSIM, s,
-           FA_TRY(launch_feature_sim(B.Xh1, B.Xh2, n1, n2, d, fdt, R1op, R2op, nL, fdt, p->alpha, B.C_node, s)));
+           FA_TRY(launch_feature_sim(B.Xh1, B.Xh2, n1, n2, d, fdt, R1op, R2op, nLop, fdt, p->alpha, B.C_node, s)));
   FA_TRY(run_propagate(A1, B.inv1, A2, B.inv2, B.C_node, B.C, p->k_node, L.chunk_rows, B.zt, s));
 
   // ---------------- initial plan S0 = mu nu^T, written as the plan of C = eps*log(n1 n2), a = b = 0

@@ -35,9 +35,19 @@ void set_error(const char *fmt, ...);
   } while (0)
 
 // Launch and check that the launch itself was accepted.
+// A dispatch counts its work-items per dimension in 32 bits: a launch past 2^32
+// work-items in one dimension does not fail, it covers only part of the range.
+// Every launch is checked here; element-wise kernels over n1 * n2 entries use
+// grid-stride loops on a capped grid (stride_grid) instead.
 #define FA_LAUNCH(kernel, grid, block, shmem, stream, ...)                          \
   do {                                                                              \
-    hipLaunchKernelGGL(kernel, grid, block, shmem, stream, __VA_ARGS__);            \
+    const dim3 fa_g_ = (grid), fa_b_ = (block);                                     \
+    FA_REQUIRE(static_cast<uint64_t>(fa_g_.x) * fa_b_.x < (1ull << 32) &&           \
+                   static_cast<uint64_t>(fa_g_.y) * fa_b_.y < (1ull << 32) &&       \
+                   static_cast<uint64_t>(fa_g_.z) * fa_b_.z < (1ull << 32),         \
+               FA_ERR_SHAPE, "launch of %s exceeds 2^32 work-items in one dimension", \
+               #kernel);                                                            \
+    hipLaunchKernelGGL(kernel, fa_g_, fa_b_, shmem, stream, __VA_ARGS__);           \
     FA_HIP(hipGetLastError());                                                      \
   } while (0)
 
@@ -194,6 +204,17 @@ __device__ inline void wave_lse2(double &m, double &s) {
 }
 
 inline int ceil_div(int64_t a, int64_t b) { return static_cast<int>((a + b - 1) / b); }
+
+// Grid of an element-wise kernel over n items, 256 threads per workgroup: at most
+// 65,536 workgroups, the kernel walks [0, n) in grid strides.
+constexpr int64_t kStrideBlocks = 1 << 16;
+inline dim3 stride_grid(int64_t n) {
+  const int64_t b = (n + 255) / 256;
+  return dim3(static_cast<unsigned>(b < kStrideBlocks ? b : kStrideBlocks));
+}
+#define FA_GRID_STRIDE(i, n)                                                                 \
+  for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < (n); \
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x)
 
 // Optional per-kernel timing with HIP events recorded on the launch stream around
 // individual launches.  Events come from a fixed pool; collect() must be called

@@ -16,6 +16,8 @@ int launch_anchor_side(const int32_t *anchors, int32_t nL, int side, int32_t *no
 int launch_partner(const int32_t *anchors, const int32_t *anchor_of1, int32_t n1, int32_t *partner,
                    hipStream_t s);
 int launch_f32_to_bf16(const float *x, int64_t n, uint16_t *y, hipStream_t s);
+// [rows x cols] -> BF16 rows of stride ld >= cols, zero-padded (16-byte rows for the MFMA GEMM).
+int launch_f32_to_bf16_rows(const float *x, int64_t rows, int32_t cols, int32_t ld, uint16_t *y, hipStream_t s);
 int launch_positional(const fa_csr *A, const float *inv_deg, const int32_t *anchor_nodes, int32_t nL,
                       double beta, int32_t k, float *R, float *R_tmp, hipStream_t s);
 int launch_sddmm(const fa_csr *A, const float *inv_deg, const float *R, int32_t nL, int32_t by_col,

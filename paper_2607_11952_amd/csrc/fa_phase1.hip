@@ -17,9 +17,7 @@ __global__ void k_inv_deg(const int64_t *__restrict__ rowptr, int32_t n, float *
 // (A is symmetric, so Abar^T has A's pattern with entry (i,k) = 1/deg_k).
 __global__ void k_colinv_weights(const int32_t *__restrict__ col, int64_t nnz,
                                  const float *__restrict__ inv, float *__restrict__ w) {
-  int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (e >= nnz) return;
-  w[e] = inv[col[e]];
+  FA_GRID_STRIDE(e, nnz) w[e] = inv[col[e]];
 }
 
 // out[i, c] = scale * inv_deg[i] * sum_{k in N(i)} X[k, c]
@@ -61,16 +59,13 @@ __global__ __launch_bounds__(256) void k_spmm_rows(const int64_t *__restrict__ r
 }
 
 __global__ void k_fill_i32(int32_t *p, int64_t n, int32_t v) {
-  int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (i < n) p[i] = v;
+  FA_GRID_STRIDE(i, n) p[i] = v;
 }
 __global__ void k_fill_f32(float *p, int64_t n, float v) {
-  int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (i < n) p[i] = v;
+  FA_GRID_STRIDE(i, n) p[i] = v;
 }
 __global__ void k_fill_f64(double *p, int64_t n, double v) {
-  int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (i < n) p[i] = v;
+  FA_GRID_STRIDE(i, n) p[i] = v;
 }
 
 // R[node_l, l] += v for every anchor l (R^(0) is one-hot at the anchor nodes).
@@ -155,8 +150,17 @@ __global__ __launch_bounds__(256) void k_l2norm(const float *__restrict__ X, int
 }
 
 __global__ void k_f32_to_bf16(const float *__restrict__ x, int64_t n, uint16_t *__restrict__ y) {
-  int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (i < n) y[i] = f32_to_bf16(x[i]);
+  FA_GRID_STRIDE(i, n) y[i] = f32_to_bf16(x[i]);
+}
+
+// Row-major [rows x cols] FP32 -> BF16 with row stride ld >= cols, pad columns zero.
+__global__ void k_f32_to_bf16_rows(const float *__restrict__ x, int64_t rows, int32_t cols, int32_t ld,
+                                   uint16_t *__restrict__ y) {
+  FA_GRID_STRIDE(i, rows * ld) {
+    const int64_t r = i / ld;
+    const int32_t c = static_cast<int32_t>(i - r * ld);
+    y[i] = c < cols ? f32_to_bf16(x[r * cols + c]) : static_cast<uint16_t>(0);
+  }
 }
 
 // ------------------------------------------------------------- launchers
@@ -169,23 +173,23 @@ int launch_inv_deg(const fa_csr *A, float *inv, hipStream_t s) {
 
 int launch_colinv_weights(const fa_csr *A, const float *inv, float *w, hipStream_t s) {
   if (A->nnz == 0) return FA_OK;
-  FA_LAUNCH(k_colinv_weights, dim3(ceil_div(A->nnz, 256)), dim3(256), 0, s, A->colidx, A->nnz, inv, w);
+  FA_LAUNCH(k_colinv_weights, stride_grid(A->nnz), dim3(256), 0, s, A->colidx, A->nnz, inv, w);
   return FA_OK;
 }
 
 int launch_fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t s) {
   if (n == 0) return FA_OK;
-  FA_LAUNCH(k_fill_i32, dim3(ceil_div(n, 256)), dim3(256), 0, s, p, n, v);
+  FA_LAUNCH(k_fill_i32, stride_grid(n), dim3(256), 0, s, p, n, v);
   return FA_OK;
 }
 int launch_fill_f32(float *p, int64_t n, float v, hipStream_t s) {
   if (n == 0) return FA_OK;
-  FA_LAUNCH(k_fill_f32, dim3(ceil_div(n, 256)), dim3(256), 0, s, p, n, v);
+  FA_LAUNCH(k_fill_f32, stride_grid(n), dim3(256), 0, s, p, n, v);
   return FA_OK;
 }
 int launch_fill_f64(double *p, int64_t n, double v, hipStream_t s) {
   if (n == 0) return FA_OK;
-  FA_LAUNCH(k_fill_f64, dim3(ceil_div(n, 256)), dim3(256), 0, s, p, n, v);
+  FA_LAUNCH(k_fill_f64, stride_grid(n), dim3(256), 0, s, p, n, v);
   return FA_OK;
 }
 
@@ -212,7 +216,13 @@ int launch_partner(const int32_t *anchors, const int32_t *anchor_of1, int32_t n1
 
 int launch_f32_to_bf16(const float *x, int64_t n, uint16_t *y, hipStream_t s) {
   if (n == 0) return FA_OK;
-  FA_LAUNCH(k_f32_to_bf16, dim3(ceil_div(n, 256)), dim3(256), 0, s, x, n, y);
+  FA_LAUNCH(k_f32_to_bf16, stride_grid(n), dim3(256), 0, s, x, n, y);
+  return FA_OK;
+}
+
+int launch_f32_to_bf16_rows(const float *x, int64_t rows, int32_t cols, int32_t ld, uint16_t *y, hipStream_t s) {
+  if (rows == 0 || ld == 0) return FA_OK;
+  FA_LAUNCH(k_f32_to_bf16_rows, stride_grid(rows * ld), dim3(256), 0, s, x, rows, cols, ld, y);
   return FA_OK;
 }
 

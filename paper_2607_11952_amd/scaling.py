@@ -8,9 +8,10 @@ N(0, 0.1^2) noise on G2, eps 0.05, 10 outer x 50 inner iterations) in both
 precision forms and records, per size: end-to-end time (HIP events, inputs
 resident), inner iterations, final marginal error, Hits@1 / Hits@10 / MRR over
 the non-anchor true pairs, and the device memory the call needs (workspace +
-plan), from which the largest n that fits in the device's memory follows.
+plan), from which the largest n that fits in the device's memory follows, with a
+dense plan buffer and with the working plan kept in the C^T buffer (no plan buffer).
 
-Usage: python -m paper_2607_11952_amd.scaling [--sizes 10000,20000,...] [--out sweep.json]
+Usage: python -m paper_2607_11952_amd.scaling [--sizes 10000,20000,...] [--plan-in-ct] [--out sweep.json]
 """
 from __future__ import annotations
 
@@ -34,22 +35,25 @@ def recipe(n: int) -> PairConfig:
 
 
 def device_bytes(inp: api.AlignInputs, p) -> int:
-    """Workspace plus plan of one fa_align call."""
+    """Workspace plus plan (none when it lives in the C^T buffer) of one fa_align call."""
     n1, n2 = inp.A1.n, inp.A2.n
-    return api.workspace_bytes(inp, p) + n1 * n2 * (2 if p.plan_dtype == binding.FA_BF16 else 4)
+    plan = 0 if p.plan_in_ct else n1 * n2 * (2 if p.plan_dtype == binding.FA_BF16 else 4)
+    return api.workspace_bytes(inp, p) + plan
 
 
-def largest_n(form: str, capacity: int) -> int:
-    """Largest n (n1 = n2, the sweep's recipe) whose fa_align call fits in `capacity` bytes
-    (bisection on the library's own workspace query; the CSR and attribute inputs add
-    well under 1% and are ignored)."""
+def largest_n(form: str, capacity: int, plan_in_ct: bool = False, avg_deg: float = 10.0, d: int = 32,
+              anchor_frac: float = 0.2) -> int:
+    """Largest n (n1 = n2; by default the sweep's recipe) whose fa_align call fits in
+    `capacity` bytes (bisection on the library's own workspace query, plus the dense plan
+    unless it lives in the C^T buffer; the CSR and attribute inputs add well under 1%
+    and are ignored)."""
     lib = api._lib()
-    p = api.params(eps=0.05, plan_dtype=form, feat_dtype=form)
-    sb = 2 if form == "bf16" else 4
+    p = api.params(eps=0.05, plan_dtype=form, feat_dtype=form, plan_in_ct=plan_in_ct)
+    sb = 0 if plan_in_ct else (2 if form == "bf16" else 4)
 
     def need(n):
-        nnz = 10 * n
-        return lib.raw("fa_align_workspace_size")(n, n, 32, int(0.2 * n), nnz, nnz, p) + n * n * sb
+        nnz = int(avg_deg * n)
+        return lib.raw("fa_align_workspace_size")(n, n, d, int(anchor_frac * n), nnz, nnz, p) + n * n * sb
 
     lo, hi = 1000, 2_000_000
     while hi - lo > 100:
@@ -61,7 +65,7 @@ def largest_n(form: str, capacity: int) -> int:
     return lo
 
 
-def run(sizes, forms=("bf16", "f32"), log=print):
+def run(sizes, forms=("bf16", "f32"), log=print, plan_in_ct=False):
     dev = torch.device("cuda:0")
     rows = []
     for n in sizes:
@@ -73,8 +77,8 @@ def run(sizes, forms=("bf16", "f32"), log=print):
         tt = torch.from_numpy(truth).to(dev)
         for form in forms:
             p = api.params(eps=cfg.eps, outer_iters=cfg.outer_iters, inner_iters=cfg.inner_iters, plan_dtype=form,
-                           feat_dtype=form)
-            al = api.Aligner(inp, p, None, tt)
+                           feat_dtype=form, plan_in_ct=plan_in_ct)
+            al = api.Aligner(inp, p, None, tt, topk=10 if plan_in_ct else 0, dense_plan=not plan_in_ct)
             torch.cuda.synchronize()
             e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
             e0.record()
@@ -82,7 +86,7 @@ def run(sizes, forms=("bf16", "f32"), log=print):
             e1.record()
             torch.cuda.synchronize()
             rk = res.rank[res.rank > 0].double()
-            row = dict(n=n, form=form, align_s=e0.elapsed_time(e1) / 1e3, inner_total=int(res.stats.inner_total),
+            row = dict(n=n, form=form, plan_in_ct=bool(plan_in_ct), align_s=e0.elapsed_time(e1) / 1e3, inner_total=int(res.stats.inner_total),
                        marg_err=float(res.stats.marg_err), hits_at_1=float((rk <= 1).double().mean()),
                        hits_at_10=float((rk <= 10).double().mean()), mrr=float((1.0 / rk).mean()),
                        device_gb=device_bytes(inp, p) / 1e9)
@@ -95,6 +99,7 @@ def run(sizes, forms=("bf16", "f32"), log=print):
         torch.cuda.empty_cache()
     cap = torch.cuda.get_device_properties(dev).total_memory
     ceiling = {f: largest_n(f, int(cap * 0.97)) for f in forms}
+    ceiling.update({f"{f}_plan_in_ct": largest_n(f, int(cap * 0.97), plan_in_ct=True) for f in forms})
     return dict(recipe=dict(kind="er", avg_deg=10, noise=0.05, d=32, sigma=0.1, anchor_frac=0.2, eps=0.05,
                             outer_iters=10, inner_iters=50),
                 rows=rows, device_memory_bytes=cap, largest_n_that_fits=ceiling)
@@ -105,10 +110,13 @@ def main():
     ap.add_argument("--sizes", default=",".join(map(str, SIZES)))
     ap.add_argument("--forms", default="bf16,f32")
     ap.add_argument("--out", default="")
+    ap.add_argument("--plan-in-ct", action="store_true",
+                    help="keep the working plan in the C^T buffer (no n1 x n2 plan; top-10 lists out)")
     args = ap.parse_args()
     log = lambda m: print(m, file=sys.stderr, flush=True)
     t0 = time.time()
-    out = run([int(x) for x in args.sizes.split(",")], tuple(args.forms.split(",")), log=log)
+    out = run([int(x) for x in args.sizes.split(",")], tuple(args.forms.split(",")), log=log,
+              plan_in_ct=args.plan_in_ct)
     out["seconds"] = time.time() - t0
     if args.out:
         with open(args.out, "w") as f:

@@ -226,3 +226,29 @@ def test_beyond_the_dense_plan_ceiling(setup, form):
     del res, val, idx, inp
     gc.collect()
     torch.cuda.empty_cache()
+
+
+def test_initial_plan_past_two_to_the_32_entries(setup):
+    """fa_align with no outer iteration returns the plan of its initial cost fill,
+    S^0 = mu nu^T (R3): every entry the same value.  At n1 = n2 = 66,000 the fill
+    covers 4.36e9 > 2^32 entries, more work-items than one dispatch dimension
+    counts; a launch sized one work-item per entry would leave the rows past the
+    first 2^32 entries unfilled (they keep the propagation scratch), which this
+    catches."""
+    import gc
+    from paper_2607_11952_amd.synth import PairConfig
+    api = setup["api"]
+    gc.collect()
+    torch.cuda.empty_cache()
+    pr = make_pair(PairConfig("fill66k", 66000, "er", 4.0, noise=0.05, d=8, sigma=0.1, anchor_frac=0.001, seed=66))
+    n = pr.n1
+    assert n * n > 2**32
+    inp = api.AlignInputs.from_pair(pr)
+    res = api.align(inp, api.params(eps=0.05, outer_iters=0, inner_iters=1))
+    torch.cuda.synchronize()
+    lo, hi = float(res.S.min()), float(res.S.max())
+    log(f"n={n}: initial plan entries in [{lo:.6e}, {hi:.6e}], mu nu^T = {1.0 / (n * n):.6e}")
+    assert lo == hi and abs(lo * n * n - 1.0) < 1e-5
+    del res, inp
+    gc.collect()
+    torch.cuda.empty_cache()

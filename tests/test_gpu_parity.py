@@ -463,6 +463,27 @@ def test_align_unequal_sizes_ragged(api, chunk):
     assert e <= 5e-3 and agree >= 0.99, (e, agree)
 
 
+@pytest.mark.parametrize("form", ["f32", "bf16"])
+@pytest.mark.parametrize("frac", [0.3, 0.05], ids=["encodings-own-buffers", "encodings-inside-C"])
+def test_align_encoding_placement(api, frac, form):
+    """The positional encodings live inside C during Phase 1 when they fit (few
+    anchors) and in buffers of their own otherwise (here 90 anchors on 300 nodes:
+    4 n |L| floats exceed the n^2 of C); both placements against the oracle (the
+    BF16 form with its argmax bar; 15 and 90 anchors are no multiples of 8, so the
+    BF16 encodings are stored with zero-padded rows)."""
+    cfg = PairConfig("e", 300, "er", 8.0, noise=0.05, d=12, sigma=0.2, anchor_frac=frac, seed=31)
+    pr = make_pair(cfg)
+    p = O.Params(eps=0.05, outer_iters=3, inner_iters=40)
+    kw = dict(plan_dtype=form, feat_dtype=form) if form == "bf16" else {}
+    ref, res = _align_both(api, pr, p, **kw)
+    agree = (_np(res.argmax) == ref["argmax"]).mean()
+    if form == "f32":
+        assert _plan_close(_np(res.S), ref["S"], 1e-4), _plan_err(_np(res.S), ref["S"])
+        assert agree == 1.0
+    else:
+        assert agree >= 0.99, agree
+
+
 def test_align_bf16_form_argmax_agreement(api):
     cfg = CONFIGS["c1"]
     pr = make_pair(cfg)
