@@ -13,7 +13,7 @@
 // gather of column l of a row block is one 512-byte piece.  The N-set is FP32 in
 // both precision forms (log P needs it near P = 0); the BF16 form stores the
 // E-set in BF16 (a 384-byte piece), which cuts stage 2's gather traffic, the
-// fabric behind L2 that bounds it, by a quarter at a relative error of 2^-9 per
+// fabric behind L2 that bounds it, by a quarter at a relative error of 2^-8 per
 // entry of Z_e (stage 2 accumulates in FP64).  Neighbour lists are uniform per
 // wavefront (one output row or column per wave), fetched 64 at a time with one
 // coalesced load and broadcast lane by lane, so no lane diverges on the power-law
