@@ -553,6 +553,65 @@ def test_align_degenerate_inputs(api, kind, plan_in_ct, monkeypatch):
         assert np.all(ref["argmax"] == 0) and np.ptp(ref["S"]) <= 1e-12 * ref["S"].max()
 
 
+@pytest.mark.parametrize("transposed", [False, True], ids=["strips", "transposed"])
+@pytest.mark.parametrize("shape", [(1, 5), (300, 257), (64, 1), (129, 1030)])
+def test_sinkhorn_additive_cost_at_large_magnitude(api, shape, transposed):
+    """C_ij = u_i + v_j with |u|, |v| up to 1000 and eps = 0.01 (exponents up to
+    2e5, far outside FP32's range): one iteration of Eq. (3) from zero duals gives
+    a_j = v_j + eps log nu - eps L and b_i = u_i + eps log mu + eps L with
+    L = LSE_i(-u_i/eps), and the plan mu nu^T exactly.  u, v are multiples of 1/64,
+    so C is exact in FP32 and the closed forms apply to the stored cost."""
+    from scipy.special import logsumexp
+    n1, n2 = shape
+    eps = 0.01
+    r = np.random.default_rng(n1 * 1000 + n2)
+    u = r.integers(-64000, 64000, n1) / 64.0
+    v = r.integers(-64000, 64000, n2) / 64.0
+    C = (u[:, None] + v[None, :]).astype(np.float32)
+    assert np.array_equal(C.astype(np.float64), u[:, None] + v[None, :])
+    Cd = torch.from_numpy(C).cuda()
+    a = torch.zeros(n2, dtype=torch.float64, device=Cd.device)
+    b = torch.zeros(n1, dtype=torch.float64, device=Cd.device)
+    it, err = api.sinkhorn(Cd, eps, a, b, 1, Ct=Cd.t().contiguous() if transposed else None)
+    L = logsumexp(-u / eps)
+    a_want = v + eps * np.log(1.0 / n2) - eps * L
+    b_want = u + eps * np.log(1.0 / n1) + eps * L
+    assert it == 1
+    np.testing.assert_allclose(a.cpu().numpy(), a_want, rtol=0, atol=1e-7)
+    np.testing.assert_allclose(b.cpu().numpy(), b_want, rtol=0, atol=1e-7)
+    S = api.plan(Cd, eps, a, b)
+    np.testing.assert_allclose(_np(S), 1.0 / (n1 * n2), rtol=2e-5)
+    assert err <= 1e-5
+
+
+def test_align_nan_input_is_a_numeric_error(api):
+    """A NaN attribute makes the cost non-finite: fa_align stops with
+    FA_ERR_NUMERIC after the first inner solve instead of returning a plan."""
+    import dataclasses
+    from paper_2607_11952_amd import binding
+    pr = make_pair(CONFIGS["c1"])
+    X1 = pr.X1.copy()
+    X1[3, 1] = np.nan
+    inp = api.AlignInputs.from_pair(dataclasses.replace(pr, X1=X1))
+    with pytest.raises(binding.FastAlignError) as ex:
+        api.align(inp, api.params(eps=0.05, outer_iters=2, inner_iters=3))
+    assert ex.value.status == binding.FA_ERR_NUMERIC
+
+
+def test_align_reports_convergence(api):
+    """The stop rule (R13) and the status: an unreachable tolerance runs every solve
+    to its cap and returns FA_WARN_NOT_CONVERGED; a tolerance met at the first
+    check stops each solve after one iteration and returns FA_OK."""
+    from paper_2607_11952_amd import binding
+    inp = api.AlignInputs.from_pair(make_pair(CONFIGS["c1"]))
+    res = api.align(inp, api.params(eps=0.05, outer_iters=2, inner_iters=3, tol=1e-14))
+    assert res.status == binding.FA_WARN_NOT_CONVERGED and res.stats.converged_all == 0
+    assert list(res.stats.inner_iters)[:2] == [3, 3] and res.stats.inner_total == 6
+    res = api.align(inp, api.params(eps=0.05, outer_iters=2, inner_iters=50, tol=10.0))
+    assert res.status == binding.FA_OK and res.stats.converged_all == 1
+    assert list(res.stats.inner_iters)[:2] == [1, 1]
+
+
 def test_align_bf16_form_argmax_agreement(api):
     cfg = CONFIGS["c1"]
     pr = make_pair(cfg)
