@@ -41,7 +41,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1)
     ap.add_argument("--warmup", type=int, default=0)
-    ap.add_argument("--workload", default="c5", help="c5 (default), c2 or c3")
+    ap.add_argument("--workload", default="cl120k", help="cl120k (default), cl20k or cl60k_50k")
     ap.add_argument("--n", type=int, default=0, help="override n1 (smaller runs of the same recipe)")
     ap.add_argument("--outer", type=int, default=0, help="override the outer iteration count")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain FP32 comparison run")
@@ -163,7 +163,7 @@ def main():
     p_plain = api.params(plan_dtype="f32", feat_dtype="f32", warm_start=False, **common)
 
     # runtime warm-up on a tiny pair (loads the code objects; not a benchmark step)
-    tiny = api.AlignInputs.from_pair(make_pair(CONFIGS["c1"], n1=200), dev)
+    tiny = api.AlignInputs.from_pair(make_pair(CONFIGS["er1k"], n1=200), dev)
     api.align(tiny, api.params(outer_iters=1, inner_iters=2))
     torch.cuda.synchronize()
 

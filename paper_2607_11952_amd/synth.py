@@ -54,16 +54,16 @@ class PairConfig:
 # pair for the reduced-precision form, the warm-start training family (template)
 # and the largest single-GPU pair.
 CONFIGS = {
-    "c1": PairConfig("er1k", 1000, "er", 8.0, noise=0.05, d=32, sigma=0.1,
+    "er1k": PairConfig("er1k", 1000, "er", 8.0, noise=0.05, d=32, sigma=0.1,
                      anchor_frac=0.10, seed=1, eps=0.05, outer_iters=10, inner_iters=50),
-    "c2": PairConfig("cl20k", 20000, "chung_lu", 12.0, noise=0.10, d=64, sigma=0.2,
+    "cl20k": PairConfig("cl20k", 20000, "chung_lu", 12.0, noise=0.10, d=64, sigma=0.2,
                      anchor_frac=0.05, seed=2, eps=0.02, outer_iters=20, inner_iters=100),
-    "c3": PairConfig("cl60k_50k", 60000, "chung_lu", 16.0, noise=0.10, keep_n2=50000,
+    "cl60k_50k": PairConfig("cl60k_50k", 60000, "chung_lu", 16.0, noise=0.10, keep_n2=50000,
                      d=128, sigma=0.2, anchor_frac=0.05, seed=3, eps=0.02,
                      outer_iters=20, inner_iters=100),
-    "c4": PairConfig("warm_train", 4000, "er", 12.0, noise=0.08, d=64, sigma=0.2,
+    "warm_train": PairConfig("warm_train", 4000, "er", 12.0, noise=0.08, d=64, sigma=0.2,
                      anchor_frac=0.05, seed=1000, eps=0.02, outer_iters=20, inner_iters=100),
-    "c5": PairConfig("cl120k", 120000, "chung_lu", 20.0, noise=0.10, d=128, sigma=0.2,
+    "cl120k": PairConfig("cl120k", 120000, "chung_lu", 20.0, noise=0.10, d=128, sigma=0.2,
                      anchor_frac=0.02, seed=5, eps=0.02, outer_iters=30, inner_iters=100),
 }
 

@@ -40,7 +40,7 @@ EPS = 0.02
 
 def family(seed: int, n: int = 0):
     r = np.random.default_rng(seed)
-    base = CONFIGS["c4"]
+    base = CONFIGS["warm_train"]
     return dataclasses.replace(
         base, n1=n or int(r.integers(2000, 8001)), kind="er" if r.random() < 0.5 else "chung_lu",
         avg_deg=float(r.integers(8, 21)), noise=float(r.uniform(0.0, 0.15)), d=64, anchor_frac=0.05, seed=seed,

@@ -39,7 +39,7 @@ def test_library_exports_every_declared_symbol(lib):
     assert set(names) == set(binding.EXPORTS)
 
 
-@pytest.mark.parametrize("cfg", ["c1", "c2"])
+@pytest.mark.parametrize("cfg", ["er1k", "cl20k"])
 def test_csr_build_bit_exact_with_oracle(lib, cfg):
     from paper_2607_11952_amd import api
     pr = make_pair(CONFIGS[cfg])

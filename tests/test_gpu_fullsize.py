@@ -32,7 +32,7 @@ def log(msg):
 @pytest.fixture(scope="module")
 def setup(lib):
     from paper_2607_11952_amd import api
-    cfg = CONFIGS["c5"]
+    cfg = CONFIGS["cl120k"]
     pr = make_pair(cfg)
     inp = api.AlignInputs.from_pair(pr)
     rp1, ci1 = O.build_csr(pr.n1, pr.edges1)
@@ -234,7 +234,7 @@ def test_beyond_the_dense_plan_ceiling(setup, form):
     api = setup["api"]
     gc.collect()
     torch.cuda.empty_cache()
-    cfg = dataclasses.replace(CONFIGS["c5"], name="cl145k", n1=BEYOND_N)
+    cfg = dataclasses.replace(CONFIGS["cl120k"], name="cl145k", n1=BEYOND_N)
     pr = make_pair(cfg)
     inp = api.AlignInputs.from_pair(pr)
     n = pr.n1

@@ -385,7 +385,7 @@ def _plan_close(S_gpu, S_ref, bound):
 def test_align_small_config_end_to_end(api, transpose_cost):
     """The small workload (ER n=1000, eps 0.05, 10 x 50): plan within 1e-4, argmax identical,
     with either column pass."""
-    cfg = CONFIGS["c1"]
+    cfg = CONFIGS["er1k"]
     pr = make_pair(cfg)
     p = O.Params(eps=cfg.eps, outer_iters=cfg.outer_iters, inner_iters=cfg.inner_iters)
     ref, res = _align_both(api, pr, p, transpose_cost=transpose_cost)
@@ -402,7 +402,7 @@ def test_align_ranks_hits_and_mrr(api):
     """fa_align's ranking of the true partners (anchors excluded) on the small
     workload: Hits@1, Hits@10 and MRR within 0.01 of the oracle's on its own final
     plan, and every rank consistent with the returned FP32 plan."""
-    cfg = CONFIGS["c1"]
+    cfg = CONFIGS["er1k"]
     pr = make_pair(cfg)
     p = O.Params(eps=cfg.eps, outer_iters=cfg.outer_iters, inner_iters=cfg.inner_iters)
     rp1, ci1 = O.build_csr(pr.n1, pr.edges1)
@@ -429,7 +429,7 @@ def test_align_small_config_carried_duals(api):
     """The small workload with every solve after the first started from the previous
     duals: same bar as the zero-start run, and the start really changes the iterates."""
     import dataclasses
-    cfg = CONFIGS["c1"]
+    cfg = CONFIGS["er1k"]
     pr = make_pair(cfg)
     p = O.Params(eps=cfg.eps, outer_iters=cfg.outer_iters, inner_iters=cfg.inner_iters, carry_duals=True)
     ref, res = _align_both(api, pr, p)
@@ -589,7 +589,7 @@ def test_align_nan_input_is_a_numeric_error(api):
     FA_ERR_NUMERIC after the first inner solve instead of returning a plan."""
     import dataclasses
     from paper_2607_11952_amd import binding
-    pr = make_pair(CONFIGS["c1"])
+    pr = make_pair(CONFIGS["er1k"])
     X1 = pr.X1.copy()
     X1[3, 1] = np.nan
     inp = api.AlignInputs.from_pair(dataclasses.replace(pr, X1=X1))
@@ -603,7 +603,7 @@ def test_align_reports_convergence(api):
     to its cap and returns FA_WARN_NOT_CONVERGED; a tolerance met at the first
     check stops each solve after one iteration and returns FA_OK."""
     from paper_2607_11952_amd import binding
-    inp = api.AlignInputs.from_pair(make_pair(CONFIGS["c1"]))
+    inp = api.AlignInputs.from_pair(make_pair(CONFIGS["er1k"]))
     res = api.align(inp, api.params(eps=0.05, outer_iters=2, inner_iters=3, tol=1e-14))
     assert res.status == binding.FA_WARN_NOT_CONVERGED and res.stats.converged_all == 0
     assert list(res.stats.inner_iters)[:2] == [3, 3] and res.stats.inner_total == 6
@@ -613,7 +613,7 @@ def test_align_reports_convergence(api):
 
 
 def test_align_bf16_form_argmax_agreement(api):
-    cfg = CONFIGS["c1"]
+    cfg = CONFIGS["er1k"]
     pr = make_pair(cfg)
     p = O.Params(eps=cfg.eps, outer_iters=5, inner_iters=50)
     ref, res = _align_both(api, pr, p, plan_dtype="bf16", feat_dtype="bf16")
@@ -622,7 +622,7 @@ def test_align_bf16_form_argmax_agreement(api):
 
 
 def test_align_deterministic(api):
-    pr = make_pair(CONFIGS["c1"])
+    pr = make_pair(CONFIGS["er1k"])
     inp = api.AlignInputs.from_pair(pr)
     cp = api.params(eps=0.05, outer_iters=3, inner_iters=20)
     r1 = api.align(inp, cp)
@@ -633,7 +633,7 @@ def test_align_deterministic(api):
 
 def test_align_rejects_bad_anchors_and_workspace(api):
     from paper_2607_11952_amd import binding
-    pr = make_pair(CONFIGS["c1"])
+    pr = make_pair(CONFIGS["er1k"])
     inp = api.AlignInputs.from_pair(pr)
     dup = inp.anchors.clone()
     dup[1, 0] = dup[0, 0]

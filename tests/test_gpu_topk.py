@@ -68,12 +68,12 @@ def test_plan_topk_exact_ties_lowest_column_first(api, n2):
 
 
 def _pair_cases():
-    return [CONFIGS["c1"],
+    return [CONFIGS["er1k"],
             PairConfig("r", 420, "chung_lu", 10.0, noise=0.1, keep_n2=333, d=16, sigma=0.2, anchor_frac=0.08, seed=21)]
 
 
 @pytest.mark.parametrize("form", ["f32", "bf16"])
-@pytest.mark.parametrize("cfg", _pair_cases(), ids=["c1-1000", "ragged-420x333"])
+@pytest.mark.parametrize("cfg", _pair_cases(), ids=["er1k", "ragged-420x333"])
 def test_align_plan_in_ct_is_identical(api, cfg, form):
     """The working plan kept in the C^T buffer (the rebuild writes C only, a transpose
     pass regenerates C^T) gives bit-identical duals, plan, argmax and ranks to the
@@ -110,7 +110,7 @@ def test_align_plan_in_ct_is_identical(api, cfg, form):
 
 def test_align_plan_in_ct_argument_checks(api):
     from paper_2607_11952_amd import binding
-    pr = make_pair(CONFIGS["c1"])
+    pr = make_pair(CONFIGS["er1k"])
     inp = api.AlignInputs.from_pair(pr)
     with pytest.raises(binding.FastAlignError) as ex:
         api.align(inp, api.params(outer_iters=1, inner_iters=1, plan_in_ct=1, transpose_cost=0), dense_plan=False)

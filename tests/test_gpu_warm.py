@@ -79,7 +79,7 @@ def test_mlp_forward_backward_adam(api, N):
 
 
 def _warm_pair():
-    cfg = CONFIGS["c1"]
+    cfg = CONFIGS["er1k"]
     return make_pair(cfg, n1=500)
 
 
@@ -87,7 +87,7 @@ def test_align_with_warm_start_matches_oracle(api):
     """The small workload (ER n = 1000, 10 x 50), first solve started from the network.
     (Shorter runs are worse conditioned: with 3 x 40 iterations on 500 nodes FP32
     storage of C alone moves the oracle's plan by 5e-5.)"""
-    pr = make_pair(CONFIGS["c1"])
+    pr = make_pair(CONFIGS["er1k"])
     prm = rand_params(7, scale=3.0, offset=1.0)
     rp1, ci1 = O.build_csr(pr.n1, pr.edges1)
     rp2, ci2 = O.build_csr(pr.n2, pr.edges2)

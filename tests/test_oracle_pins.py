@@ -191,7 +191,7 @@ def test_cost_terms_brute_force():
 def test_nbr_product_conserves_mass():
     # With no isolated node, every column of Abar1 and Abar2 rows is a distribution:
     # sum(Abar1^T S Abar2) = 1^T Abar1^T S Abar2 1 = (Abar1 1)^T S (Abar2 1) = sum(S).
-    pr = make_pair(CONFIGS["c1"])
+    pr = make_pair(CONFIGS["er1k"])
     rp1, ci1 = O.build_csr(pr.n1, pr.edges1)
     deg = np.diff(rp1)
     if (deg == 0).any():
@@ -368,7 +368,7 @@ def test_permutation_equivariance():
 
 
 def test_noise_free_pair_recovers_the_permutation():
-    cfg = CONFIGS["c1"]
+    cfg = CONFIGS["er1k"]
     import dataclasses
     cfg0 = dataclasses.replace(cfg, n1=300, noise=0.0, sigma=0.0)
     pr = make_pair(cfg0)
@@ -428,7 +428,7 @@ def test_single_entry_forms_match_the_dense_oracle():
     """The per-entry forms used for sampled checks at full size equal the dense steps
     (themselves pinned above) at every sampled (i, j) of a small ragged pair."""
     import dataclasses
-    cfg = dataclasses.replace(CONFIGS["c1"], n1=90, kind="chung_lu", keep_n2=70, anchor_frac=0.1, seed=41)
+    cfg = dataclasses.replace(CONFIGS["er1k"], n1=90, kind="chung_lu", keep_n2=70, anchor_frac=0.1, seed=41)
     pr = make_pair(cfg)
     p = O.Params(eps=0.1, outer_iters=1, inner_iters=5, k_r=4)
     rp1, ci1 = O.build_csr(pr.n1, pr.edges1)
