@@ -6,20 +6,23 @@
 
 namespace fa {
 
-// Grid-stride sum of a float buffer: four 16-byte streaming loads in flight per
-// thread per step, one partial per thread (so nothing is optimised away).
+// Grid-stride sum of a float buffer: eight 16-byte streaming loads in flight per
+// thread per step (the fastest plain read found on this part: 2-8 loads in flight,
+// 2k-64k workgroups, streaming or cached loads were compared), one partial per
+// thread (so nothing is optimised away).
 __global__ __launch_bounds__(256) void k_stream_read(const float *__restrict__ x, size_t n4,
                                                      float *__restrict__ partial) {
+  constexpr int U = 8;
   const size_t tid = blockIdx.x * 256ull + threadIdx.x;
   const size_t stride = gridDim.x * 256ull;
   float s = 0.f;
   size_t i = tid;
-  for (; i + 3 * stride < n4; i += 4 * stride) {
-    f32x4 v[4];
+  for (; i + (U - 1) * stride < n4; i += U * stride) {
+    f32x4 v[U];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) v[u] = ld_stream4(x + 4 * (i + u * stride));
+    for (int u = 0; u < U; ++u) v[u] = ld_stream4(x + 4 * (i + u * stride));
 #pragma unroll
-    for (int u = 0; u < 4; ++u) s += (v[u].x + v[u].y) + (v[u].z + v[u].w);
+    for (int u = 0; u < U; ++u) s += (v[u].x + v[u].y) + (v[u].z + v[u].w);
   }
   for (; i < n4; i += stride) {
     const f32x4 v = ld_stream4(x + 4 * i);

@@ -612,6 +612,18 @@ def test_align_reports_convergence(api):
     assert list(res.stats.inner_iters)[:2] == [1, 1]
 
 
+@pytest.mark.parametrize("n4,nblocks", [(1, 1), (1000, 3), (64 * 256 * 8 * 5 + 77, 64)])
+def test_stream_read_covers_every_element_once(api, n4, nblocks):
+    """The read-rate utility behind the benchmark's measured ceiling: on a buffer of
+    ones its per-thread partials add up to the element count exactly (main loop of
+    eight loads in flight plus the tail), so the timed pass reads every byte once."""
+    x = torch.ones(4 * n4, dtype=torch.float32, device="cuda")
+    part = torch.full((nblocks * 256,), -1.0, dtype=torch.float32, device="cuda")
+    api.stream_read(x, part, nblocks)
+    torch.cuda.synchronize()
+    assert float(part.double().sum()) == 4 * n4 and bool((part >= 0).all())
+
+
 def test_align_bf16_form_argmax_agreement(api):
     cfg = CONFIGS["er1k"]
     pr = make_pair(cfg)
