@@ -90,3 +90,54 @@ def test_plan_topk_rejects_bad_arguments_before_any_device_work(lib):
     assert f(None, 4, 8, 0.1, None, None, 3, None, None, None) == binding.FA_ERR_ARG   # null pointers
     assert f(None, 4, 8, -1.0, None, None, 3, None, None, None) == binding.FA_ERR_ARG
     assert f(None, 0, 8, 0.1, None, None, 3, None, None, None) == binding.FA_OK        # no rows: nothing to do
+
+
+C_CONSUMER = r"""
+#include <stdio.h>
+#include <string.h>
+#include "fastalign.h"
+
+int main(void) {
+  fa_params p;
+  fa_default_params(&p);
+  if (!(p.eps > 0.0) || p.transpose_cost != 1 || p.plan_in_ct != 0) return 2;
+  /* triangle 0-1-2 plus a pendant 3-2, a loop and a duplicate */
+  const int64_t e[] = {0, 1, 1, 2, 2, 0, 3, 2, 1, 1, 1, 0};
+  int64_t rowptr[5], nnz = -1;
+  int32_t col[16];
+  if (fa_csr_build(4, 6, e, rowptr, col, 16, &nnz) != FA_OK) return 3;
+  printf("%lld", (long long)nnz);
+  for (int i = 0; i < 5; ++i) printf(" %lld", (long long)rowptr[i]);
+  for (int k = 0; k < nnz; ++k) printf(" %d", col[k]);
+  printf("\n");
+  if (fa_csr_build(4, 1, (const int64_t[]){0, 9}, rowptr, col, 16, &nnz) != FA_ERR_ARG) return 4;
+  if (strlen(fa_last_error()) == 0) return 5;
+  if (fa_align_workspace_size(100, 80, 8, 5, 600, 500, &p) == 0) return 6;
+  if (fa_plan_topk(NULL, 4, 8, 0.1, NULL, NULL, 65, NULL, NULL, NULL) != FA_ERR_ARG) return 7;
+  return 0;
+}
+"""
+
+
+def test_plain_c_consumer_links_and_runs_host_entry_points(lib, tmp_path):
+    """The boundary is a C ABI: a C99 program that includes only include/fastalign.h
+    and links libfastalign.so builds with gcc and runs the host-side entry points
+    (defaults, the CSR builder against the oracle's CSR, argument rejection with a
+    message, the workspace query) on a machine without a GPU."""
+    import shutil
+    import subprocess
+    if shutil.which("gcc") is None:
+        pytest.skip("no C compiler")
+    from paper_2607_11952_amd import binding
+    src = tmp_path / "consumer.c"
+    src.write_text(C_CONSUMER)
+    exe = tmp_path / "consumer"
+    libdir = os.path.dirname(binding.LIB_PATH)
+    subprocess.run(["gcc", "-std=c99", "-Wall", "-Werror", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe),
+                    "-L", libdir, "-lfastalign", f"-Wl,-rpath,{libdir}"], check=True, capture_output=True)
+    out = subprocess.run([str(exe)], capture_output=True, text=True, timeout=60)
+    assert out.returncode == 0, (out.returncode, out.stderr)
+    vals = [int(v) for v in out.stdout.split()]
+    e = np.array([[0, 1], [1, 2], [2, 0], [3, 2], [1, 1], [1, 0]])
+    rp, ci = O.build_csr(4, e)
+    assert vals[0] == rp[-1] and vals[1:6] == list(rp) and vals[6:] == list(ci)
