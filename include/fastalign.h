@@ -83,9 +83,12 @@ typedef struct {
   int32_t warm_start; /* 0: cold duals; 1: learned row duals for the first solve */
   int32_t chunk_rows; /* rows per Phase-2 chunk (0: automatic) */
   int32_t profile;    /* 1: time every launch with HIP events (fa_stats.kernel_ms) */
-  int32_t carry_duals;/* 0: every inner solve starts from a = b = 0; 1: solves after the first
-                         start from the previous solve's final duals.  The fixed point of each
-                         solve is the same; only the iterates before convergence differ. */
+  int32_t dual_start; /* start of the inner solves after the first (fa_dual_start):
+                         FA_START_ZERO a = b = 0; FA_START_CARRY the previous solve's final
+                         duals; FA_START_MEAN the mean of all earlier solves' final duals.
+                         Each solve's fixed point is the same from any start (its duals are
+                         unique up to a constant shift); only iterates before convergence
+                         differ. */
   int32_t transpose_cost; /* 1: fa_align keeps C^T beside C (one more n1*n2 FP32 buffer in
                          the workspace) and runs the a-update on its rows; 0: column
                          strips of C (less memory, a slower a-update) */
@@ -95,15 +98,28 @@ typedef struct {
                          pass regenerates C^T.  No n1*n2 plan buffer is needed (S_out may be
                          NULL; the plan is handed out as top-k lists), results are identical
                          to plan_in_ct = 0, one extra pass over C per outer iteration. */
+  int32_t warm_fallback; /* 1 (with warm_start and tol > 0): when the solve started from the
+                         learned duals misses tol, the same solve is rerun from a = b = 0 and
+                         the run keeps whichever ends with the smaller marginal error
+                         (fa_stats.fell_back = 2 when the cold solve is kept) */
 } fa_params;
+
+/* Starts of the inner solves after the first (fa_params.dual_start). */
+typedef enum { FA_START_ZERO = 0, FA_START_CARRY = 1, FA_START_MEAN = 2 } fa_dual_start;
 
 /* Run statistics returned by fa_align (host struct). */
 typedef struct {
   int32_t outer_done;
-  int32_t inner_total;      /* Sinkhorn iterations summed over outer iterations */
-  int32_t fell_back;        /* 1 if the learned start was non-finite and the solve started cold */
+  int32_t inner_total;      /* Sinkhorn iterations summed over outer iterations (both solves
+                               of the first one when the cold rerun happened) */
+  int32_t fell_back;        /* learned start: 0 kept, 1 non-finite prediction (the solve ran
+                               cold), 2 its solve missed tol and the cold rerun ended closer */
   int32_t converged_all;    /* 1 if every inner solve met tol */
   double marg_err;          /* L1 column-marginal error of the last inner solve */
+  int32_t warm_iters;       /* iterations of the solve from the learned start (-1: none) */
+  int32_t cold_iters;       /* iterations of the cold rerun of that solve (-1: none) */
+  double warm_err;          /* their final marginal errors (NaN: not run) */
+  double cold_err;
   double phase_ms[4];       /* Phase 1, cost rebuild, Sinkhorn, plan (device time) */
   int32_t inner_iters[64];  /* per outer iteration (first 64) */
   double inner_err[64];
@@ -122,7 +138,8 @@ const char *fa_last_error(void);
 /* Fill *p with this library's defaults: eps 0.05, alpha 0.5, beta 0.15,
  * lambda_e = lambda_n = lambda_a = 1, lambda_p = eps_anchor = eps,
  * delta_nbr 1e-30, tol 0, k_r 10, k_node 1, 10 outer x 50 inner iterations,
- * check_every 1, FP32 plan and features, feat_l2norm 1, cold start. */
+ * check_every 1, FP32 plan and features, feat_l2norm 1, cold start, zero starts
+ * for later solves, transpose_cost 1, warm_fallback 1. */
 void fa_default_params(fa_params *p);
 
 /* 0 if the current HIP device is a gfx950 GPU, else FA_ERR_DEVICE. */
@@ -290,13 +307,47 @@ size_t fa_align_workspace_size(int32_t n1, int32_t n2, int32_t d, int32_t nL,
  *   topk (0 = none, else 1..min(64, n2)), topk_val float[n1*topk], topk_idx
  *     int32[n1*topk] (out): the final plan's top-k lists, as in fa_plan_topk
  *   stats host fa_stats (out), may be NULL
- * The call synchronises the stream once at the end to fill stats.  Returns
+ * The call synchronises the stream after the anchor check, after every outer
+ * iteration and at the end.  Returns FA_ERR_NUMERIC as soon as an inner solve
+ * ends with a non-finite marginal error (the outputs are then partial), and
  * FA_WARN_NOT_CONVERGED if tol > 0 and some inner solve missed it. */
 int fa_align(const fa_csr *A1, const fa_csr *A2, const float *X1, const float *X2, int32_t d,
              const int32_t *anchors, int32_t nL, const fa_params *p, const float *mlp_weights,
              void *S_out, double *a_out, double *b_out, int32_t *argmax_out, const int32_t *truth,
              int32_t *rank_out, int32_t topk, float *topk_val, int32_t *topk_idx, fa_stats *stats,
              void *ws, size_t ws_bytes, void *stream);
+
+/* Algorithm 1 one outer iteration at a time: fa_align is exactly
+ *   fa_align_begin; fa_align_step for t = 0 .. T-1; fa_align_end(steps = T)
+ * on the same arguments, with the final argmax/truth/rank passed to the last step.
+ * A caller can time, inspect or stop between outer iterations.  Every call takes
+ * the same A1, A2, d, nL, p, S_out, a_out, b_out and workspace (the workspace holds
+ * the state between calls; its layout depends on p, which must not change).
+ *
+ * fa_align_begin: anchor check (synchronises once), Phase 1, S^0 = mu nu^T in the
+ *   working plan (S_out, or the C^T buffer with p->plan_in_ct), warm-start inputs.
+ * fa_align_step: outer iteration t (cost rebuild, inner solve from the start the
+ *   params select, plan).  argmax_out/truth/rank_out (nullable; truth and rank_out
+ *   together) are written from this step's plan, as fa_align does on its last step.
+ *   Synchronises at the end; returns FA_ERR_NUMERIC if the solve's marginal error
+ *   is not finite.  acc (host, nullable): with p->profile its phase_ms,
+ *   kernel_ms and kernel_calls accumulate this step's device times.
+ * fa_align_end: after `steps` steps (0: writes the S^0 plan and argmax into S_out
+ *   like fa_align with outer_iters = 0); with p->plan_in_ct a non-NULL S_out
+ *   receives the final dense plan; top-k lists as in fa_align; stats (nullable)
+ *   receives every field except phase_ms, kernel_ms and kernel_calls.  Returns
+ *   FA_WARN_NOT_CONVERGED like fa_align. */
+int fa_align_begin(const fa_csr *A1, const fa_csr *A2, const float *X1, const float *X2, int32_t d,
+                   const int32_t *anchors, int32_t nL, const fa_params *p, void *S_out, double *a_out,
+                   double *b_out, void *ws, size_t ws_bytes, void *stream);
+int fa_align_step(const fa_csr *A1, const fa_csr *A2, int32_t d, int32_t nL, const fa_params *p,
+                  const float *mlp_weights, int32_t t, void *S_out, double *a_out, double *b_out,
+                  int32_t *argmax_out, const int32_t *truth, int32_t *rank_out, fa_stats *acc, void *ws,
+                  size_t ws_bytes, void *stream);
+int fa_align_end(const fa_csr *A1, const fa_csr *A2, int32_t d, int32_t nL, const fa_params *p, int32_t steps,
+                 void *S_out, const double *a_out, const double *b_out, int32_t *argmax_out,
+                 const int32_t *truth, int32_t *rank_out, int32_t topk, float *topk_val, int32_t *topk_idx,
+                 fa_stats *stats, void *ws, size_t ws_bytes, void *stream);
 
 /* ----------------------------------------------------------------------- */
 /* Learned warm start: per-node inputs and a 3-layer MLP                     */

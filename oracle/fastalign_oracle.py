@@ -39,11 +39,15 @@ with their reasons in the design notes of the repository):
 * R12 argmax ties resolve to the lowest column index.
 * R16 The top-k plan lists a row's k largest plan entries, larger log S first and,
       on equal log S, the lower column first (R12 extended to the whole list).
-* R14 (variant) With carry_duals, every inner solve after the first starts from
-      the final duals of the previous one instead of zeros.  A solve run to
-      convergence reaches the same optimum from any start (its duals are unique up
-      to a constant shift that the plan and the cost update do not see), so the
-      variant changes only iterates that stop before convergence.
+* R14 (variants) dual_start = "carry": every inner solve after the first starts
+      from the final duals of the previous one instead of zeros; "mean": from the
+      mean of the final duals of all earlier solves.  A solve run to convergence
+      reaches the same optimum from any start (its duals are unique up to a
+      constant shift that the plan and the cost update do not see), so the
+      variants change only iterates that stop before convergence.
+* R17 A learned start (b_init) of the first solve whose solve misses tol is
+      rerun from zero duals, and the run keeps whichever of the two solves ends
+      with the smaller marginal error (the cold start stays the reference).
 """
 from __future__ import annotations
 
@@ -56,7 +60,7 @@ import scipy.sparse as sp
 __all__ = [
     "Params", "build_csr", "row_normalized", "onehot_anchors", "positional_encoding",
     "l2_normalize_rows", "feature_similarity", "propagate", "anchor_cost", "intra_costs",
-    "cost_update", "lse", "sinkhorn", "plan", "marginal_error", "align",
+    "cost_update", "lse", "sinkhorn", "plan", "marginal_error", "initial_log_plan", "align",
     "similarity_entry", "propagate_entry", "intra_row_entries", "cost_entry", "row_dual_entry", "plan_entry",
     "true_partner_ranks", "hits_at_k", "mean_reciprocal_rank",
 ]
@@ -80,7 +84,8 @@ class Params:
     outer_iters: int = 10
     inner_iters: int = 50
     feat_l2norm: bool = True
-    carry_duals: bool = False            # R14 variant: later solves start from the previous duals
+    dual_start: str = "zero"             # R14: "zero", "carry" or "mean" start of the solves after the first
+    warm_fallback: bool = True           # R17: rerun a learned start's solve cold when it misses tol
 
     @property
     def lp(self) -> float:
@@ -306,6 +311,11 @@ def phase1(n1, rowptr1, colidx1, n2, rowptr2, colidx2, X1, X2, anchors, p: Param
                 C_node=C_node, C_anc=C_anc, C1=C1, C2=C2)
 
 
+def initial_log_plan(n1: int, n2: int) -> np.ndarray:
+    """log S^0 for S^0 = mu nu^T with the uniform marginals of Eq. (1) (reading R3)."""
+    return np.full((n1, n2), -np.log(float(n1) * float(n2)))
+
+
 def align(n1, rowptr1, colidx1, n2, rowptr2, colidx2, X1, X2, anchors, p: Params,
           b_init: Optional[np.ndarray] = None, keep_history: bool = False):
     """Algorithm 1: Phase 1 once, then outer iterations of Phase 2 + Phase 3.
@@ -314,21 +324,40 @@ def align(n1, rowptr1, colidx1, n2, rowptr2, colidx2, X1, X2, anchors, p: Params
     Returns a dict with S, a, b, argmax, the last cost C, per-outer inner
     iteration counts and marginal errors.
     """
+    if p.dual_start not in ("zero", "carry", "mean"):
+        raise ValueError(f"unknown dual_start {p.dual_start!r}")
     ph = phase1(n1, rowptr1, colidx1, n2, rowptr2, colidx2, X1, X2, anchors, p)
-    logS = np.full((n1, n2), -np.log(float(n1) * float(n2)))
+    logS = initial_log_plan(n1, n2)
     S = np.exp(logS)
     iters, errs, hist = [], [], []
     a = np.zeros(n2)
     b = np.zeros(n1)
+    solved_a, solved_b = [], []
+    warm = dict(warm_iters=-1, warm_err=float("nan"), cold_iters=-1, cold_err=float("nan"), fell_back=0)
     C = None
     for t in range(p.outer_iters):
         C = cost_update(ph["C_node"], ph["C_anc"], ph["C1"], ph["C2"], ph["Abar1"],
                         ph["Abar2"], S, logS, p)
-        if t > 0 and p.carry_duals:
+        a0 = b0 = None                      # zero start
+        if t == 0 and b_init is not None:
+            b0 = b_init
+        elif t > 0 and p.dual_start == "carry":
             a0, b0 = a, b
-        else:
-            a0, b0 = None, (b_init if (t == 0 and b_init is not None) else None)
+        elif t > 0 and p.dual_start == "mean":
+            a0 = sum(solved_a) / len(solved_a)
+            b0 = sum(solved_b) / len(solved_b)
         a, b, it, err = sinkhorn(C, p.eps, p.inner_iters, p.tol, a0, b0)
+        if t == 0 and b_init is not None:
+            warm.update(warm_iters=it, warm_err=err)
+            if p.warm_fallback and p.tol > 0 and not err <= p.tol:
+                ac, bc, itc, errc = sinkhorn(C, p.eps, p.inner_iters, p.tol)
+                warm.update(cold_iters=itc, cold_err=errc)
+                if errc < err:
+                    a, b, err = ac, bc, errc
+                    warm["fell_back"] = 2
+                it += itc
+        solved_a.append(a)
+        solved_b.append(b)
         logS = (a[None, :] + b[:, None] - C) / p.eps
         S = np.exp(logS)
         iters.append(it)
@@ -337,7 +366,7 @@ def align(n1, rowptr1, colidx1, n2, rowptr2, colidx2, X1, X2, anchors, p: Params
             hist.append(dict(C=C.copy(), a=a.copy(), b=b.copy()))
     argmax = np.argmax(S, axis=1) if n2 > 0 else np.zeros(n1, dtype=np.int64)
     return dict(S=S, a=a, b=b, argmax=argmax, C=C, iters=iters, errs=errs,
-                phase1=ph, history=hist)
+                phase1=ph, history=hist, **warm)
 
 
 # ----------------------------------------------------------------------------

@@ -88,7 +88,10 @@ def params(**kw) -> B.fa_params:
     for k, v in kw.items():
         if k in ("plan_dtype", "feat_dtype") and isinstance(v, str):
             v = {"f32": B.FA_F32, "bf16": B.FA_BF16}[v]
-        if k in ("feat_l2norm", "warm_start", "profile", "carry_duals", "transpose_cost", "plan_in_ct"):
+        if k == "dual_start" and isinstance(v, str):
+            v = {"zero": B.FA_START_ZERO, "carry": B.FA_START_CARRY, "mean": B.FA_START_MEAN}[v]
+        if k in ("feat_l2norm", "warm_start", "profile", "dual_start", "transpose_cost", "plan_in_ct",
+                 "warm_fallback"):
             v = int(v)
         setattr(p, k, v)
     if "lambda_p" not in kw:
@@ -268,6 +271,36 @@ class Aligner:
         self.rank = torch.empty(n1, dtype=torch.int32, device=dev) if truth is not None else None
         self.topk_val = torch.empty((n1, self.topk), dtype=torch.float32, device=dev) if self.topk else None
         self.topk_idx = torch.empty((n1, self.topk), dtype=torch.int32, device=dev) if self.topk else None
+
+    # ---- one outer iteration at a time (fa_align_begin / fa_align_step / fa_align_end)
+    def _common(self):
+        inp = self.inp
+        return (C.byref(inp.A1.c), C.byref(inp.A2.c), int(inp.X1.shape[1]), int(inp.anchors.shape[0]),
+                C.byref(self.p))
+
+    def begin(self):
+        """Phase 1 and S^0 (synchronises once for the anchor check)."""
+        inp = self.inp
+        _lib().call("fa_align_begin", C.byref(inp.A1.c), C.byref(inp.A2.c), _ptr(inp.X1), _ptr(inp.X2),
+                    int(inp.X1.shape[1]), _ptr(inp.anchors), int(inp.anchors.shape[0]), C.byref(self.p),
+                    _ptr(self.S), _ptr(self.a), _ptr(self.b), _ptr(self.ws), self.ws_bytes, _stream())
+
+    def step(self, t: int, last: bool = False, acc: Optional[B.fa_stats] = None):
+        """Outer iteration t; with last=True its plan pass also writes argmax (and ranks)."""
+        A1, A2, d, nL, p = self._common()
+        _lib().call("fa_align_step", A1, A2, d, nL, p, _ptr(self.mlp), int(t), _ptr(self.S), _ptr(self.a),
+                    _ptr(self.b), _ptr(self.argmax) if last else None, _ptr(self.truth) if last else None,
+                    _ptr(self.rank) if last else None, C.byref(acc) if acc is not None else None, _ptr(self.ws),
+                    self.ws_bytes, _stream())
+
+    def end(self, steps: int, stats: Optional[B.fa_stats] = None) -> AlignResult:
+        A1, A2, d, nL, p = self._common()
+        st = stats if stats is not None else B.fa_stats()
+        status = _lib().call("fa_align_end", A1, A2, d, nL, p, int(steps), _ptr(self.S), _ptr(self.a), _ptr(self.b),
+                             _ptr(self.argmax) if steps == 0 else None, _ptr(self.truth) if steps == 0 else None,
+                             _ptr(self.rank) if steps == 0 else None, self.topk, _ptr(self.topk_val),
+                             _ptr(self.topk_idx), C.byref(st), _ptr(self.ws), self.ws_bytes, _stream())
+        return AlignResult(self.S, self.a, self.b, self.argmax, st, status, self.rank, self.topk_val, self.topk_idx)
 
     def run(self) -> AlignResult:
         st = B.fa_stats()

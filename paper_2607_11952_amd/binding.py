@@ -16,6 +16,7 @@ FA_OK, FA_WARN_NOT_CONVERGED = 0, 1
 FA_ERR_ARG, FA_ERR_SHAPE, FA_ERR_CSR, FA_ERR_WORKSPACE = -1, -2, -3, -4
 FA_ERR_NUMERIC, FA_ERR_HIP, FA_ERR_DEVICE = -6, -7, -8
 FA_F32, FA_BF16, FA_F64 = 0, 1, 2
+FA_START_ZERO, FA_START_CARRY, FA_START_MEAN = 0, 1, 2
 
 EXPORTS = [
     "fa_last_error", "fa_default_params", "fa_device_check", "fa_csr_build", "fa_row_normalize",
@@ -24,6 +25,7 @@ EXPORTS = [
     "fa_align_workspace_size", "fa_align", "fa_node_feature_dim", "fa_node_features_workspace_size",
     "fa_node_features", "fa_mlp_param_count", "fa_mlp_act_floats", "fa_mlp_forward",
     "fa_mlp_backward", "fa_adam_step", "fa_stream_read", "fa_plan_topk",
+    "fa_align_begin", "fa_align_step", "fa_align_end",
 ]
 
 
@@ -40,16 +42,19 @@ class fa_params(C.Structure):
         ("check_every", C.c_int32), ("plan_dtype", C.c_int32), ("feat_dtype", C.c_int32),
         ("feat_l2norm", C.c_int32), ("warm_start", C.c_int32), ("chunk_rows", C.c_int32),
         ("profile", C.c_int32),
-        ("carry_duals", C.c_int32),
+        ("dual_start", C.c_int32),
         ("transpose_cost", C.c_int32),
         ("plan_in_ct", C.c_int32),
+        ("warm_fallback", C.c_int32),
     ]
 
 
 class fa_stats(C.Structure):
     _fields_ = [
         ("outer_done", C.c_int32), ("inner_total", C.c_int32), ("fell_back", C.c_int32),
-        ("converged_all", C.c_int32), ("marg_err", C.c_double), ("phase_ms", C.c_double * 4),
+        ("converged_all", C.c_int32), ("marg_err", C.c_double),
+        ("warm_iters", C.c_int32), ("cold_iters", C.c_int32), ("warm_err", C.c_double), ("cold_err", C.c_double),
+        ("phase_ms", C.c_double * 4),
         ("inner_iters", C.c_int32 * 64), ("inner_err", C.c_double * 64),
         ("kernel_ms", C.c_double * 10), ("kernel_calls", C.c_int32 * 10),
     ]
@@ -83,6 +88,12 @@ _SIGS = {
     "fa_align_workspace_size": (_SZ, [_I32, _I32, _I32, _I32, _I64, _I64, C.POINTER(fa_params)]),
     "fa_align": (C.c_int, [C.POINTER(fa_csr), C.POINTER(fa_csr), _P, _P, _I32, _P, _I32, C.POINTER(fa_params),
                            _P, _P, _P, _P, _P, _P, _P, _I32, _P, _P, C.POINTER(fa_stats), _P, _SZ, _P]),
+    "fa_align_begin": (C.c_int, [C.POINTER(fa_csr), C.POINTER(fa_csr), _P, _P, _I32, _P, _I32,
+                                 C.POINTER(fa_params), _P, _P, _P, _P, _SZ, _P]),
+    "fa_align_step": (C.c_int, [C.POINTER(fa_csr), C.POINTER(fa_csr), _I32, _I32, C.POINTER(fa_params), _P, _I32,
+                                _P, _P, _P, _P, _P, _P, C.POINTER(fa_stats), _P, _SZ, _P]),
+    "fa_align_end": (C.c_int, [C.POINTER(fa_csr), C.POINTER(fa_csr), _I32, _I32, C.POINTER(fa_params), _I32, _P, _P,
+                               _P, _P, _P, _P, _I32, _P, _P, C.POINTER(fa_stats), _P, _SZ, _P]),
     "fa_node_feature_dim": (_I32, []),
     "fa_node_features_workspace_size": (_SZ, [_I32]),
     "fa_node_features": (C.c_int, [C.POINTER(fa_csr), _P, _P, _I32, _P, _P, _I32, _P, _P, _SZ, _P]),

@@ -47,9 +47,10 @@ extern "C" void fa_default_params(fa_params *p) {
   p->warm_start = 0;
   p->chunk_rows = 0;
   p->profile = 0;
-  p->carry_duals = 0;
+  p->dual_start = FA_START_ZERO;
   p->transpose_cost = 1;
   p->plan_in_ct = 0;
+  p->warm_fallback = 1;
 }
 
 extern "C" int fa_device_check(void) {

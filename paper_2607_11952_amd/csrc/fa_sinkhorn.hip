@@ -57,11 +57,15 @@ static SinkLayout sink_layout(int32_t n1, int32_t n2) {
   return L;
 }
 
-size_t sinkhorn_ws_bytes(int32_t n1, int32_t n2) {
+// The column partials pm/ps serve only the strip-based column pass; a caller that
+// always passes C^T (transposed_only) needs none of them.
+static size_t sink_scratch_bytes(int32_t n1, int32_t n2, bool transposed_only) {
   SinkLayout L = sink_layout(n1, n2);
   Sizer z;
-  z.take<double>(static_cast<size_t>(L.nsplit) * n2);
-  z.take<double>(static_cast<size_t>(L.nsplit) * n2);
+  if (!transposed_only) {
+    z.take<double>(static_cast<size_t>(L.nsplit) * n2);
+    z.take<double>(static_cast<size_t>(L.nsplit) * n2);
+  }
   z.take<double>(n2);
   z.take<double>((L.nmerge > L.ncolt ? L.nmerge : L.ncolt) + 1);
   z.take<SinkCtl>(1);
@@ -69,10 +73,12 @@ size_t sinkhorn_ws_bytes(int32_t n1, int32_t n2) {
   return z.off;
 }
 
-int carve_sinkhorn(Carver &cv, int32_t n1, int32_t n2, SinkWs &w) {
+size_t sinkhorn_ws_bytes(int32_t n1, int32_t n2) { return sink_scratch_bytes(n1, n2, false); }
+
+static int carve_sink(Carver &cv, int32_t n1, int32_t n2, SinkWs &w, bool transposed_only) {
   SinkLayout L = sink_layout(n1, n2);
-  w.pm = cv.take<double>(static_cast<size_t>(L.nsplit) * n2);
-  w.ps = cv.take<double>(static_cast<size_t>(L.nsplit) * n2);
+  w.pm = transposed_only ? nullptr : cv.take<double>(static_cast<size_t>(L.nsplit) * n2);
+  w.ps = transposed_only ? nullptr : cv.take<double>(static_cast<size_t>(L.nsplit) * n2);
   w.a_next = cv.take<double>(n2);
   w.errp = cv.take<double>((L.nmerge > L.ncolt ? L.nmerge : L.ncolt) + 1);
   w.ctl = reinterpret_cast<int32_t *>(cv.take<SinkCtl>(1));
@@ -81,6 +87,8 @@ int carve_sinkhorn(Carver &cv, int32_t n1, int32_t n2, SinkWs &w) {
   w.nerrblk = L.nmerge;
   return cv.ok ? FA_OK : FA_ERR_WORKSPACE;
 }
+
+int carve_sinkhorn(Carver &cv, int32_t n1, int32_t n2, SinkWs &w) { return carve_sink(cv, n1, n2, w, false); }
 
 // Vector store of V consecutive plan entries (one 16-byte FP32 or 8-byte BF16
 // store per lane for V = 4).

@@ -47,8 +47,11 @@ def family(seed: int, n: int = 0):
         eps=EPS)
 
 
-def first_solve(inp, inner: int, mlp=None, tol: float = 0.0):
-    p = api.params(eps=EPS, outer_iters=1, inner_iters=inner, tol=tol, warm_start=mlp is not None)
+def first_solve(inp, inner: int, mlp=None, tol: float = 0.0, fallback: bool = False):
+    """One outer iteration (the first inner solve); with a network, the learned start
+    alone (fallback False) or with the library's cold rerun when it misses tol."""
+    p = api.params(eps=EPS, outer_iters=1, inner_iters=inner, tol=tol, warm_start=mlp is not None,
+                   warm_fallback=int(fallback))
     return api.align(inp, p, mlp=mlp)
 
 
@@ -121,12 +124,19 @@ def evaluate(prm: torch.Tensor, seeds, n: int, K: int, device, log=print, tol: f
         wt = first_solve(inp, cap, mlp=prm, tol=tol)
         wt_it, wt_err = int(wt.stats.inner_iters[0]), float(wt.stats.inner_err[0])
         agree_tol = float((wt.argmax == ct_arg).float().mean())
+        # the product path: learned start, cold rerun when it misses tol (both solves counted)
+        fb = first_solve(inp, cap, mlp=prm, tol=tol, fallback=True)
+        fb_it, fb_err, fb_fell = int(fb.stats.inner_iters[0]), float(fb.stats.inner_err[0]), int(fb.stats.fell_back)
+        agree_fb = float((fb.argmax == ct_arg).float().mean())
         rows.append(dict(seed=s, n=n, K=K, err_cold=e_cold, err_warm=e_warm, iters_warm_to_cold_err=it_warm,
                          argmax_agreement=agree, tol=tol, cap=cap, iters_cold_to_tol=ct_it, err_cold_at_stop=ct_err,
-                         iters_warm_to_tol=wt_it, err_warm_at_stop=wt_err, argmax_agreement_at_tol=agree_tol))
+                         iters_warm_to_tol=wt_it, err_warm_at_stop=wt_err, argmax_agreement_at_tol=agree_tol,
+                         iters_fallback=fb_it, err_fallback=fb_err, fell_back=fb_fell,
+                         argmax_agreement_fallback=agree_fb))
         log(f"[eval] seed {s}: err after {K}: cold {e_cold:.3e} warm {e_warm:.3e}; warm reaches the cold error in "
             f"{it_warm} iterations; argmax agreement {agree:.4f}; to {tol:g}: cold {ct_it} ({ct_err:.2e}) "
-            f"warm {wt_it} ({wt_err:.2e}), agreement {agree_tol:.4f}")
+            f"warm {wt_it} ({wt_err:.2e}), agreement {agree_tol:.4f}; with fallback {fb_it} ({fb_err:.2e}, "
+            f"fell_back {fb_fell})")
     return rows
 
 
@@ -141,7 +151,14 @@ def summarize(rows):
                 mean_iters_cold_to_tol=float(ic.mean()), mean_iters_warm_to_tol=float(iw.mean()),
                 iteration_ratio=float(ic.sum() / max(iw.sum(), 1.0)),
                 min_argmax_agreement_at_tol=float(np.min(f("argmax_agreement_at_tol"))),
-                mean_argmax_agreement_at_tol=float(np.mean(f("argmax_agreement_at_tol"))))
+                mean_argmax_agreement_at_tol=float(np.mean(f("argmax_agreement_at_tol"))),
+                warm_reached_tol=int(sum(r["err_warm_at_stop"] <= r["tol"] for r in rows)),
+                cold_reached_tol=int(sum(r["err_cold_at_stop"] <= r["tol"] for r in rows)),
+                mean_iters_fallback=float(np.mean(f("iters_fallback"))),
+                fallback_reached_tol=int(sum(r["err_fallback"] <= r["tol"] for r in rows)),
+                fell_back_pairs=int(sum(r["fell_back"] != 0 for r in rows)),
+                iteration_ratio_with_fallback=float(ic.sum() / max(sum(f("iters_fallback")), 1.0)),
+                min_argmax_agreement_fallback=float(np.min(f("argmax_agreement_fallback"))))
 
 
 def main():

@@ -367,7 +367,7 @@ def _align_both(api, pr, p, **kw):
     inp = api.AlignInputs.from_pair(pr)
     cp = api.params(eps=p.eps, alpha=p.alpha, beta=p.beta, lambda_e=p.lambda_e, lambda_n=p.lambda_n,
                     lambda_a=p.lambda_a, k_r=p.k_r, k_node=p.k_node, outer_iters=p.outer_iters,
-                    inner_iters=p.inner_iters, tol=p.tol, carry_duals=int(p.carry_duals), **kw)
+                    inner_iters=p.inner_iters, tol=p.tol, dual_start=p.dual_start, **kw)
     res = api.align(inp, cp)
     return ref, res
 
@@ -425,13 +425,15 @@ def test_align_ranks_hits_and_mrr(api):
     assert np.all((got >= lo) & (got <= hi))   # FP32 ties of S leave the exact rank anywhere in between
 
 
-def test_align_small_config_carried_duals(api):
+@pytest.mark.parametrize("start", ["carry", "mean"])
+def test_align_small_config_later_solve_starts(api, start):
     """The small workload with every solve after the first started from the previous
-    duals: same bar as the zero-start run, and the start really changes the iterates."""
+    duals (or the mean of all earlier solves' duals): same bar as the zero-start
+    run, and the start really changes the iterates."""
     import dataclasses
     cfg = CONFIGS["er1k"]
     pr = make_pair(cfg)
-    p = O.Params(eps=cfg.eps, outer_iters=cfg.outer_iters, inner_iters=cfg.inner_iters, carry_duals=True)
+    p = O.Params(eps=cfg.eps, outer_iters=cfg.outer_iters, inner_iters=cfg.inner_iters, dual_start=start)
     ref, res = _align_both(api, pr, p)
     S = _np(res.S)
     assert _plan_close(S, ref["S"], 1e-4), np.abs(S - ref["S"]).max() / ref["S"].max()
@@ -440,7 +442,7 @@ def test_align_small_config_carried_duals(api):
         assert abs(res.stats.inner_err[t] - ref["errs"][t]) <= 1e-3 * ref["errs"][t] + 1e-8
     rp1, ci1 = O.build_csr(pr.n1, pr.edges1)
     rp2, ci2 = O.build_csr(pr.n2, pr.edges2)
-    zero = O.align(pr.n1, rp1, ci1, pr.n2, rp2, ci2, pr.X1, pr.X2, pr.anchors, dataclasses.replace(p, carry_duals=False))
+    zero = O.align(pr.n1, rp1, ci1, pr.n2, rp2, ci2, pr.X1, pr.X2, pr.anchors, dataclasses.replace(p, dual_start="zero"))
     assert abs(zero["errs"][1] - ref["errs"][1]) > 1e-3 * zero["errs"][1]
 
 

@@ -1,0 +1,172 @@
+"""GPU tests of Algorithm 1 driven one outer iteration at a time (fa_align_begin /
+fa_align_step / fa_align_end), of the cold fallback of the learned start, and of the
+per-iteration check for non-finite marginal errors."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import fastalign_oracle as O
+from oracle import warm_oracle as W
+from paper_2607_11952_amd.synth import CONFIGS, make_pair
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def api(lib):
+    from paper_2607_11952_amd import api as A
+    return A
+
+
+def _np(t):
+    return t.float().cpu().numpy().astype(np.float64) if t.dtype == torch.bfloat16 else t.cpu().numpy()
+
+
+def rand_params(seed, scale=1.0, offset=0.0):
+    r = np.random.default_rng(seed)
+    return W.pack(r.standard_normal((W.FEAT, W.HID)) / math.sqrt(W.FEAT), r.standard_normal(W.HID) * 0.1,
+                  r.standard_normal((W.HID, W.HID)) / math.sqrt(W.HID), r.standard_normal(W.HID) * 0.1,
+                  r.standard_normal(W.HID) / math.sqrt(W.HID), 0.2, scale, offset)
+
+
+def T32(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()
+
+
+@pytest.mark.parametrize("form", ["f32-carry-warm", "bf16-mean", "f32-plan-in-ct-zero"])
+def test_stepwise_equals_align(api, form):
+    """begin + T steps + end on one workspace reproduces fa_align bit for bit: plan,
+    duals, argmax, ranks, top-k lists and the per-solve iteration counts and errors."""
+    pr = make_pair(CONFIGS["er1k"], n1=600)
+    inp = api.AlignInputs.from_pair(pr)
+    truth = pr.truth.astype(np.int32).copy()
+    truth[pr.anchors[:, 0]] = -1
+    truth = torch.from_numpy(truth).cuda()
+    kw = dict(eps=0.05, outer_iters=4, inner_iters=30, tol=1e-9)
+    mlp = None
+    lean = {}
+    if form == "f32-carry-warm":
+        p = api.params(dual_start="carry", warm_start=1, **kw)
+        mlp = T32(rand_params(3, scale=2.0))
+    elif form == "bf16-mean":
+        p = api.params(dual_start="mean", plan_dtype="bf16", feat_dtype="bf16", **kw)
+    else:
+        p = api.params(plan_in_ct=1, **kw)
+        lean = dict(topk=5)
+    ref = api.Aligner(inp, p, mlp, truth, **lean).run()
+    ref = {k: (v.clone() if torch.is_tensor(v) else v) for k, v in vars(ref).items()}
+    al = api.Aligner(inp, p, mlp, truth, **lean)
+    al.begin()
+    for t in range(p.outer_iters):
+        al.step(t, last=(t == p.outer_iters - 1))
+    got = al.end(p.outer_iters)
+    for k in ("S", "a", "b", "argmax", "rank", "topk_val", "topk_idx"):
+        if ref[k] is not None:
+            assert torch.equal(getattr(got, k), ref[k]), k
+    assert got.status == ref["status"]
+    assert list(got.stats.inner_iters) == list(ref["stats"].inner_iters)
+    assert list(got.stats.inner_err) == list(ref["stats"].inner_err)
+    assert got.stats.fell_back == ref["stats"].fell_back
+
+
+def test_stepwise_zero_steps_is_the_uniform_plan(api):
+    """end() after begin() alone returns S^0 = mu nu^T, as fa_align with no outer iteration."""
+    pr = make_pair(CONFIGS["er1k"], n1=300)
+    inp = api.AlignInputs.from_pair(pr)
+    p = api.params(eps=0.05, outer_iters=0)
+    al = api.Aligner(inp, p)
+    al.begin()
+    res = al.end(0)
+    S = _np(res.S)
+    np.testing.assert_allclose(S, 1.0 / (pr.n1 * pr.n2), rtol=2e-6)
+    assert np.all(_np(res.argmax) == 0)   # every entry ties: the lowest column
+
+
+def _oracle_warm(pr, prm, p):
+    rp1, ci1 = O.build_csr(pr.n1, pr.edges1)
+    rp2, ci2 = O.build_csr(pr.n2, pr.edges2)
+    F = W.node_features(pr.n1, rp1, ci1, pr.X1, W.gauss_projection(pr.X1.shape[1]), pr.anchors[:, 0])
+    y, _ = W.mlp_forward(np.asarray(prm, np.float32).astype(np.float64), F)
+    ref = O.align(pr.n1, rp1, ci1, pr.n2, rp2, ci2, pr.X1, pr.X2, pr.anchors, p, b_init=p.eps * y)
+    return ref
+
+
+def test_warm_fallback_keeps_the_cold_solve_when_it_ends_closer(api):
+    """A poor learned start (random network, outputs scaled far off) misses the
+    tolerance: the first solve is rerun from zero duals, the cold solve ends closer
+    to the marginals and is kept (fell_back = 2), as the oracle decides; the run is
+    then bit-identical to a cold run, and both solves' iterations are counted."""
+    pr = make_pair(CONFIGS["er1k"], n1=500)
+    inp = api.AlignInputs.from_pair(pr)
+    prm = rand_params(11, scale=1000.0, offset=5.0)
+    kw = dict(eps=0.05, outer_iters=2, inner_iters=25, tol=1e-12)
+    ref = _oracle_warm(pr, prm, O.Params(**kw))
+    assert ref["fell_back"] == 2 and ref["warm_err"] > 4 * ref["cold_err"]
+    warm = api.align(inp, api.params(warm_start=1, **kw), mlp=T32(prm))
+    cold = api.align(inp, api.params(**kw))
+    assert warm.stats.fell_back == 2
+    assert warm.stats.warm_iters == 25 and warm.stats.cold_iters == 25
+    assert warm.stats.inner_iters[0] == 50 and warm.stats.inner_total == 50 + 25
+    assert warm.stats.warm_err > warm.stats.cold_err
+    assert abs(warm.stats.warm_err - ref["warm_err"]) <= 1e-3 * ref["warm_err"]
+    assert abs(warm.stats.cold_err - ref["cold_err"]) <= 1e-3 * ref["cold_err"] + 1e-9
+    assert torch.equal(warm.S, cold.S) and torch.equal(warm.a, cold.a) and torch.equal(warm.b, cold.b)
+    np.testing.assert_array_equal(_np(warm.argmax), ref["argmax"])
+
+
+def test_warm_fallback_keeps_the_learned_solve_when_it_ends_closer(api):
+    """The trained network on a held-out pair of its family: its solve misses the
+    (unreachable) tolerance, the cold rerun ends farther from the marginals, so the
+    learned solve is kept (fell_back = 0), as the oracle decides; the result equals a
+    run without the fallback bit for bit, and the plan matches the oracle's."""
+    from paper_2607_11952_amd import warm as warmio
+    from paper_2607_11952_amd.train_warm import family
+    prm = warmio.read_weights()
+    assert prm is not None
+    pr = make_pair(family(5103, 1500))
+    kw = dict(eps=0.02, outer_iters=1, inner_iters=20, tol=1e-12)
+    ref = _oracle_warm(pr, prm, O.Params(**kw))
+    assert ref["fell_back"] == 0 and ref["cold_err"] > 10 * ref["warm_err"]
+    inp = api.AlignInputs.from_pair(pr)
+    got = api.align(inp, api.params(warm_start=1, **kw), mlp=T32(prm))
+    nofb = api.align(inp, api.params(warm_start=1, warm_fallback=0, **kw), mlp=T32(prm))
+    assert got.stats.fell_back == 0 and got.stats.cold_iters == 20 and got.stats.inner_iters[0] == 40
+    assert nofb.stats.cold_iters == -1 and nofb.stats.inner_iters[0] == 20
+    assert torch.equal(got.S, nofb.S) and torch.equal(got.b, nofb.b)
+    assert abs(got.stats.warm_err - ref["warm_err"]) <= 2e-3 * ref["warm_err"]
+    S = _np(got.S)
+    assert np.abs(S - ref["S"]).max() / ref["S"].max() <= 1e-4
+    np.testing.assert_array_equal(_np(got.argmax), ref["argmax"])
+
+
+def test_warm_start_met_tolerance_needs_no_rerun(api):
+    """A learned start whose solve meets the tolerance is kept without a cold rerun."""
+    from paper_2607_11952_amd import warm as warmio
+    from paper_2607_11952_amd.train_warm import family
+    prm = warmio.read_weights()
+    pr = make_pair(family(5103, 1500))
+    inp = api.AlignInputs.from_pair(pr)
+    got = api.align(inp, api.params(eps=0.02, outer_iters=1, inner_iters=400, tol=1e-3, warm_start=1),
+                    mlp=T32(prm))
+    assert got.stats.warm_err <= 1e-3 and got.stats.cold_iters == -1 and got.stats.fell_back == 0
+    assert got.stats.inner_iters[0] == got.stats.warm_iters
+
+
+def test_nan_stops_at_the_first_outer_iteration(api):
+    """A NaN attribute makes the first solve's marginal error non-finite: the first
+    step already fails with FA_ERR_NUMERIC (so fa_align stops there instead of
+    running every outer iteration)."""
+    import dataclasses
+    from paper_2607_11952_amd import binding
+    pr = make_pair(CONFIGS["er1k"], n1=300)
+    X1 = pr.X1.copy()
+    X1[3, 1] = np.nan
+    inp = api.AlignInputs.from_pair(dataclasses.replace(pr, X1=X1))
+    al = api.Aligner(inp, api.params(eps=0.05, outer_iters=30, inner_iters=3))
+    al.begin()
+    with pytest.raises(binding.FastAlignError) as ex:
+        al.step(0)
+    assert ex.value.status == binding.FA_ERR_NUMERIC
+    assert "outer iteration 0" in str(ex.value)

@@ -334,11 +334,13 @@ def test_outer_loop_fixed_cost_equals_sinkhorn_at_eps_over_t():
     assert np.allclose(out["S"], O.plan(C0, a, b, p.eps / T), atol=1e-11)
 
 
-def test_carry_over_start_reaches_the_same_plans():
+@pytest.mark.parametrize("start", ["carry", "mean"])
+def test_later_solve_starts_reach_the_same_plans(start):
     """Each inner solve has one optimum whatever its start (up to a constant shift
     of the duals that neither the plan nor the cost update sees): run to convergence,
-    starts carried over from the previous solve and zero starts give the same plan
-    at every outer iteration, and the carried start needs fewer iterations."""
+    starts carried over from the previous solve (or the mean of all earlier solves'
+    duals) and zero starts give the same plan at every outer iteration, and the
+    non-zero start needs fewer iterations."""
     import dataclasses
     n = 14
     e1, e2, X1, X2, L, pi = _small_pair(n=n, seed=34, anchors=2, noise=0.3)
@@ -346,7 +348,7 @@ def test_carry_over_start_reaches_the_same_plans():
     # converge to 1e-13 (-log(delta) entries slow Sinkhorn down by orders of magnitude)
     p0 = O.Params(eps=0.3, lambda_n=0.0, outer_iters=3, inner_iters=20000, tol=1e-13, k_r=3)
     zero = _run(n, e1, n, e2, X1, X2, L, p0, keep_history=True)
-    carry = _run(n, e1, n, e2, X1, X2, L, dataclasses.replace(p0, carry_duals=True), keep_history=True)
+    carry = _run(n, e1, n, e2, X1, X2, L, dataclasses.replace(p0, dual_start=start), keep_history=True)
     for hz, hc in zip(zero["history"], carry["history"]):
         Sz = O.plan(hz["C"], hz["a"], hz["b"], p0.eps)
         Sc = O.plan(hc["C"], hc["a"], hc["b"], p0.eps)
