@@ -258,6 +258,27 @@ int fa_sinkhorn(const float *C, const float *Ct, int32_t n1, int32_t n2, double 
                 double *dev_err, int32_t *host_iters, double *host_err, void *ws,
                 size_t ws_bytes, void *stream);
 
+/* fa_sinkhorn for callers that cannot allocate device memory: code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc.  Same
+ * arguments, kernels and results (bit for bit) as fa_sinkhorn, minus the
+ * workspace and the host copies: its scratch (the candidate a, the per-workgroup
+ * error partials, the loop's control word and, without Ct, the per-column
+ * partials) lives in a static device array of FA_SINKHORN_NOALLOC_SCRATCH bytes,
+ * one per GPU, held until the process ends.  The call allocates nothing
+ * (no hipMalloc, no library allocation) and never synchronises; read dev_iters /
+ * dev_err after the stream has passed it.  Sizes whose scratch exceeds the array
+ * (fa_sinkhorn_noalloc_need(n1, n2, Ct != NULL) > FA_SINKHORN_NOALLOC_SCRATCH) are
+ * refused with FA_ERR_SHAPE: with Ct that is n2 beyond ~1.8 million, without Ct
+ * the per-column partials (16 * n2 bytes per row split) limit it to small n2.
+ * All calls on one GPU share its array: calls that overlap in time on one GPU
+ * (other streams or threads) race and must be serialised by the caller.  The
+ * first call on a device looks the array's device address up (once per device). */
+#define FA_SINKHORN_NOALLOC_SCRATCH (16u << 20)
+size_t fa_sinkhorn_noalloc_need(int32_t n1, int32_t n2, int32_t transposed);
+int fa_sinkhorn_noalloc(const float *C, const float *Ct, int32_t n1, int32_t n2, double eps, double *a,
+                        double *b, int32_t max_iter, double tol, int32_t check_every, int32_t *dev_iters,
+                        double *dev_err, void *stream);
+
 /* Plan recovery S_ij = exp((a_j + b_i - C_ij)/eps) (Eq. (4)) stored as s_dtype
  * (FA_F32 or FA_BF16, round-to-nearest-even).  If argmax is non-NULL it also
  * writes argmax_j (a_j + b_i - C_ij) per row i (lowest j on ties), int32[n1].

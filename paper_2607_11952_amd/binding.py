@@ -17,6 +17,7 @@ FA_ERR_ARG, FA_ERR_SHAPE, FA_ERR_CSR, FA_ERR_WORKSPACE = -1, -2, -3, -4
 FA_ERR_NUMERIC, FA_ERR_HIP, FA_ERR_DEVICE = -6, -7, -8
 FA_F32, FA_BF16, FA_F64 = 0, 1, 2
 FA_START_ZERO, FA_START_CARRY, FA_START_MEAN = 0, 1, 2
+FA_SINKHORN_NOALLOC_SCRATCH = 16 << 20
 
 EXPORTS = [
     "fa_last_error", "fa_default_params", "fa_device_check", "fa_csr_build", "fa_row_normalize",
@@ -25,7 +26,7 @@ EXPORTS = [
     "fa_align_workspace_size", "fa_align", "fa_node_feature_dim", "fa_node_features_workspace_size",
     "fa_node_features", "fa_mlp_param_count", "fa_mlp_act_floats", "fa_mlp_forward",
     "fa_mlp_backward", "fa_adam_step", "fa_stream_read", "fa_plan_topk",
-    "fa_align_begin", "fa_align_step", "fa_align_end",
+    "fa_align_begin", "fa_align_step", "fa_align_end", "fa_sinkhorn_noalloc_need", "fa_sinkhorn_noalloc",
 ]
 
 
@@ -83,6 +84,8 @@ _SIGS = {
                           C.POINTER(fa_params), _P, _P, _P, _SZ, _P]),
     "fa_sinkhorn_workspace_size": (_SZ, [_I32, _I32]),
     "fa_sinkhorn": (C.c_int, [_P, _P, _I32, _I32, _D, _P, _P, _I32, _D, _I32, _P, _P, _P, _P, _P, _SZ, _P]),
+    "fa_sinkhorn_noalloc_need": (_SZ, [_I32, _I32, _I32]),
+    "fa_sinkhorn_noalloc": (C.c_int, [_P, _P, _I32, _I32, _D, _P, _P, _I32, _D, _I32, _P, _P, _P]),
     "fa_plan": (C.c_int, [_P, _I32, _I32, _D, _P, _P, _P, _I32, _P, _P, _P, _P]),
     "fa_plan_topk": (C.c_int, [_P, _I32, _I32, _D, _P, _P, _I32, _P, _P, _P]),
     "fa_align_workspace_size": (_SZ, [_I32, _I32, _I32, _I32, _I64, _I64, C.POINTER(fa_params)]),

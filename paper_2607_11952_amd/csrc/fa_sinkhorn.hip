@@ -23,6 +23,8 @@
 //
 // The loop never waits for the host: a device control word marks convergence and
 // every later kernel of the loop returns at its first instruction.
+#include <mutex>
+
 #include "fa_common.h"
 #include "fa_internal.h"
 
@@ -676,4 +678,61 @@ extern "C" int fa_plan(const float *C, int32_t n1, int32_t n2, double eps, const
   FA_REQUIRE(C && a && b && S, FA_ERR_ARG, "fa_plan: null pointer");
   FA_REQUIRE((truth == nullptr) == (rank == nullptr), FA_ERR_ARG, "fa_plan: truth and rank go together");
   return run_plan(C, n1, n2, eps, a, b, S, s_dtype, argmax, truth, rank, static_cast<hipStream_t>(stream));
+}
+
+// ---------------------------------------------------------------- no allocation
+
+// Scratch of fa_sinkhorn_noalloc: one copy per GPU, held until the process ends.
+// Host code reaches it only through the address hipGetSymbolAddress returns for
+// the current device (the array's name on the host is not a device address).
+static __device__ __align__(256) unsigned char scratch[FA_SINKHORN_NOALLOC_SCRATCH];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of the current GPU's scratch array, looked up once per device.
+int device_scratch(void **out) {
+  int dev = -1;
+  FA_HIP(hipGetDevice(&dev));
+  FA_REQUIRE(dev >= 0 && dev < kMaxDevices, FA_ERR_ARG, "fa_sinkhorn_noalloc: device %d out of range", dev);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void *ptr = nullptr;
+    FA_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    FA_REQUIRE(ptr != nullptr, FA_ERR_HIP, "fa_sinkhorn_noalloc: no device address for the scratch array");
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return FA_OK;
+}
+}  // namespace
+
+extern "C" size_t fa_sinkhorn_noalloc_need(int32_t n1, int32_t n2, int32_t transposed) {
+  if (n1 <= 0 || n2 <= 0) return 0;
+  return sink_scratch_bytes(n1, n2, transposed != 0);
+}
+
+extern "C" int fa_sinkhorn_noalloc(const float *C, const float *Ct, int32_t n1, int32_t n2, double eps, double *a,
+                                   double *b, int32_t max_iter, double tol, int32_t check_every, int32_t *dev_iters,
+                                   double *dev_err, void *stream) {
+  FA_REQUIRE(n1 > 0 && n2 > 0, FA_ERR_SHAPE, "fa_sinkhorn_noalloc: n1 = %d, n2 = %d must be positive", n1, n2);
+  FA_REQUIRE(eps > 0 && max_iter >= 0 && check_every >= 1 && tol >= 0, FA_ERR_ARG,
+             "fa_sinkhorn_noalloc: need eps > 0, max_iter >= 0, check_every >= 1, tol >= 0");
+  FA_REQUIRE(C && a && b && dev_iters && dev_err, FA_ERR_ARG, "fa_sinkhorn_noalloc: null pointer");
+  const bool tr = Ct != nullptr;
+  const size_t need = sink_scratch_bytes(n1, n2, tr);
+  FA_REQUIRE(need <= FA_SINKHORN_NOALLOC_SCRATCH, FA_ERR_SHAPE,
+             "fa_sinkhorn_noalloc: %d x %d needs %zu bytes of scratch %s, the static array holds %zu "
+             "(use fa_sinkhorn with a workspace)",
+             n1, n2, need, tr ? "with C^T" : "without C^T (column partials)",
+             static_cast<size_t>(FA_SINKHORN_NOALLOC_SCRATCH));
+  void *ptr = nullptr;
+  FA_TRY(device_scratch(&ptr));
+  Carver cv(ptr, FA_SINKHORN_NOALLOC_SCRATCH);
+  SinkWs w;
+  FA_TRY(carve_sink(cv, n1, n2, w, tr));
+  return run_sinkhorn(C, Ct, n1, n2, eps, a, b, max_iter, tol, check_every, dev_iters, dev_err, w,
+                      static_cast<hipStream_t>(stream));
 }
