@@ -8,13 +8,16 @@ A step is one outer iteration of Algorithm 1 on resident state (cost rebuild fro
 the sparse adjacencies and the dense plan, the inner Sinkhorn solve, the plan),
 called through the C ABI (fa_align_step).  The headline form (plan in BF16, FP32
 cost and SpMM intermediates, FP64 duals, learned warm start of the first solve
-when trained weights are present, the --start policy for the later solves) runs
+when trained weights are present with the cold rerun as its fallback, later solves
+started from the mean of the earlier solves' duals) runs
 ONE alignment: fa_align_begin (Phase 1), then outer iterations 0..T-1 as steps
 (the first W are the untimed warm-up, the next K are timed together), then
 fa_align_end.  `value` is that whole alignment's device time (the metric is an
 align time, lower is better); `ms_per_step` the mean of the K timed steps.  The
 plain form (FP32 plan, cold starts, the paper's method) is one fa_align call timed
-beside it, then the FP64 oracle on the host cores on a bounded sample.  Inputs are
+beside it, and an FP32 run with the headline's start policy separates the effect
+of precision from that of the starts; then the FP64 oracle on the host cores on a
+bounded sample.  Inputs are
 resident in HBM before any timed region.  A wall-clock budget skips the optional
 legs (plain form, CPU baseline) if they would not fit, and the line is always
 printed.
@@ -56,8 +59,10 @@ def parse():
     ap.add_argument("--no-plain", action="store_true", help="skip the plain FP32 comparison run")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cold", action="store_true", help="headline form without the learned warm start")
-    ap.add_argument("--start", default="carry", choices=["zero", "carry", "mean"],
+    ap.add_argument("--start", default="mean", choices=["zero", "carry", "mean"],
                     help="headline form: start of the inner solves after the first")
+    ap.add_argument("--no-f32-mean", action="store_true",
+                    help="skip the FP32 run with the headline's start policy (the precision-only comparison)")
     ap.add_argument("--plan-in-ct", action="store_true",
                     help="keep the working plan in the C^T buffer: no n1 x n2 plan buffer, top-10 lists out")
     ap.add_argument("--budget-s", type=float, default=540.0,
@@ -201,10 +206,12 @@ def main():
     mlp = None if args.cold else warm.load_weights(dev)
     common = dict(eps=cfg.eps, outer_iters=T, inner_iters=cfg.inner_iters, tol=1e-6, check_every=1, profile=1,
                   plan_in_ct=args.plan_in_ct)
-    lean = dict(topk=10, dense_plan=False) if args.plan_in_ct else {}
+    # top-2 lists of the final plan give each row's margin log(S_top / S_second)
+    lean = dict(topk=10, dense_plan=False) if args.plan_in_ct else dict(topk=2)
     p_head = api.params(plan_dtype="bf16", feat_dtype="bf16", warm_start=mlp is not None, dual_start=args.start,
                         **common)
     p_plain = api.params(plan_dtype="f32", feat_dtype="f32", warm_start=False, dual_start="zero", **common)
+    p_f32s = api.params(plan_dtype="f32", feat_dtype="f32", warm_start=False, dual_start=args.start, **common)
 
     # runtime warm-up on a tiny pair (loads the code objects; not a benchmark step)
     tiny = api.AlignInputs.from_pair(make_pair(CONFIGS["er1k"], n1=200), dev)
@@ -276,23 +283,24 @@ def main():
         head["note"] = f"{n_outer} outer iterations ran; align_s covers Phase 1 and the first {T}"
     head["ranking"] = ranking(res.rank)
     head_argmax = res.argmax.clone()
+    head_margin = margins(res)
     head["accuracy_vs_truth"] = accuracy(head_argmax)
     log(f"headline alignment: {align_ms / 1e3:.3f} s, inner iterations {res.stats.inner_total}, "
         f"last marginal error {res.stats.marg_err:.2e}, Hits@1 {head['ranking']['hits_at_1']:.4f}")
     del al, res
     torch.cuda.empty_cache()
 
-    # ---------------- plain FP32 form (the paper's method), one fa_align call
-    plain = None
-    agree = None
+    # ---------------- FP32 forms, one fa_align call each: the plain form (the paper's
+    # method: cold starts) and, for the precision-only comparison, the headline's start
+    # policy with an FP32 plan and operands (no learned start)
     skipped = []
-    est_plain = 1.15 * align_ms / 1e3 + 15.0
-    if args.no_plain:
-        skipped.append("plain (--no-plain)")
-    elif time.time() - T_START + est_plain > args.budget_s:
-        skipped.append(f"plain (needs ~{est_plain:.0f} s, over the {args.budget_s:.0f} s budget)")
-    else:
-        al = api.Aligner(inp, p_plain, None, test_truth, **lean)
+
+    def full_run(name, p):
+        est = 1.15 * align_ms / 1e3 + 15.0
+        if time.time() - T_START + est > args.budget_s:
+            skipped.append(f"{name} (needs ~{est:.0f} s, over the {args.budget_s:.0f} s budget)")
+            return None, None
+        al = api.Aligner(inp, p, None, test_truth, **lean)
         torch.cuda.synchronize()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record()
@@ -300,18 +308,28 @@ def main():
         e1.record()
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1)
-        plain = dict(align_s=ms / 1e3, outer_iters_per_s=T / (ms / 1e3), **solve_summary(res.stats, T),
-                     kernels=kernel_table(res.stats, pair, inp.A1.nnz, inp.A2.nnz, p_plain, binding),
-                     phase_ms=dict(phase1=res.stats.phase_ms[0], cost=res.stats.phase_ms[1],
-                                   sinkhorn=res.stats.phase_ms[2], plan=res.stats.phase_ms[3]),
-                     status=int(res.status))
-        plain["ranking"] = ranking(res.rank)
-        agree = float((res.argmax == head_argmax).float().mean().item())
-        plain["accuracy_vs_truth"] = accuracy(res.argmax)
-        log(f"plain FP32: {ms / 1e3:.3f} s, inner iterations {res.stats.inner_total}, "
-            f"argmax agreement with headline {agree:.4f}")
+        out = dict(align_s=ms / 1e3, outer_iters_per_s=T / (ms / 1e3), **solve_summary(res.stats, T),
+                   kernels=kernel_table(res.stats, pair, inp.A1.nnz, inp.A2.nnz, p, binding),
+                   phase_ms=dict(phase1=res.stats.phase_ms[0], cost=res.stats.phase_ms[1],
+                                 sinkhorn=res.stats.phase_ms[2], plan=res.stats.phase_ms[3]),
+                   status=int(res.status), ranking=ranking(res.rank), accuracy_vs_truth=accuracy(res.argmax))
+        out.update(agreement_with_headline(res.argmax, head_argmax, head_margin, margins(res)))
+        log(f"{name}: {ms / 1e3:.3f} s, inner iterations {res.stats.inner_total}, last marginal error "
+            f"{res.stats.marg_err:.2e}, argmax agreement with headline {out['argmax_agreement']:.4f}")
         del al, res
         torch.cuda.empty_cache()
+        return out, out["argmax_agreement"]
+
+    plain, agree = (None, None)
+    if args.no_plain:
+        skipped.append("plain (--no-plain)")
+    else:
+        plain, agree = full_run("plain FP32", p_plain)
+    f32s = None
+    if args.no_f32_mean or args.start == "zero":
+        skipped.append("f32 with the headline start (--no-f32-mean or start zero)")
+    else:
+        f32s, _ = full_run(f"FP32, {args.start} start", p_f32s)
 
     # ---------------- roofline of the dominant kernel of the timed steps
     kt = head["kernels_timed_steps"]
@@ -349,11 +367,32 @@ def main():
                             step="one outer iteration (cost rebuild + inner solve + plan) of the headline form",
                             value="device time of the whole headline alignment (Phase 1 + all outer iterations)"),
                 warm_start=mlp is not None, dual_start=args.start, plan_in_ct=args.plan_in_ct, headline=head,
-                plain_fp32=plain, argmax_agreement=agree, speedup_vs_plain=(plain["align_s"] / head["align_s"]
-                                                                            if plain else None),
+                plain_fp32=plain, fp32_same_start=f32s, argmax_agreement=agree,
+                speedup_vs_plain=(plain["align_s"] / head["align_s"] if plain else None),
                 spmm_gbps=spmm, roofline=roofline, cpu_baseline=cpu, skipped=skipped,
                 wall_s=time.time() - T_START)
     print(json.dumps(line), flush=True)
+
+
+def margins(res):
+    """Per row, log(S_top / S_second) of the final plan from its top-2 lists (None without them)."""
+    import torch
+    if res.topk_val is None or res.topk_val.shape[1] < 2:
+        return None
+    v = res.topk_val.double()
+    return torch.log(v[:, 0] / v[:, 1].clamp_min(1e-300))
+
+
+def agreement_with_headline(am, head_am, head_margin, margin):
+    """Argmax agreement with the headline form, overall and on the rows that both plans
+    resolve: top entry above the second by more than 1 and 4 nats in both."""
+    out = dict(argmax_agreement=float((am == head_am).float().mean().item()))
+    if margin is not None and head_margin is not None:
+        for m in (1.0, 4.0):
+            rows = (margin > m) & (head_margin > m)
+            out[f"resolved_rows_{m:g}nat"] = float(rows.float().mean().item())
+            out[f"agreement_on_resolved_{m:g}nat"] = float((am[rows] == head_am[rows]).float().mean().item())
+    return out
 
 
 def measure_read_ceiling(api, torch, dev, gib=32, reps=5):

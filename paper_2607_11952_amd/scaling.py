@@ -110,6 +110,7 @@ def main():
     ap.add_argument("--sizes", default=",".join(map(str, SIZES)))
     ap.add_argument("--forms", default="bf16,f32")
     ap.add_argument("--out", default="")
+    ap.add_argument("--md", default="", help="also write a markdown summary of the sweep to this path")
     ap.add_argument("--plan-in-ct", action="store_true",
                     help="keep the working plan in the C^T buffer (no n1 x n2 plan; top-10 lists out)")
     args = ap.parse_args()
@@ -121,7 +122,34 @@ def main():
     if args.out:
         with open(args.out, "w") as f:
             json.dump(out, f, indent=1)
+    if args.md:
+        with open(args.md, "w") as f:
+            f.write(markdown(out, " ".join(sys.argv[1:])))
     print(json.dumps(out))
+
+
+def markdown(out, argv: str) -> str:
+    """Per-size table of a sweep record (time, inner iterations, Hits@1, MRR, device memory)."""
+    r = out["recipe"]
+    lines = [f"# Erdos-Renyi scalability sweep on one MI355X",
+             "",
+             f"Command (repository root): `python -m paper_2607_11952_amd.scaling {argv}`",
+             "",
+             f"Recipe: ER average degree {r['avg_deg']}, {r['noise']:.0%} edge noise, d = {r['d']} "
+             f"(sigma {r['sigma']}), {r['anchor_frac']:.0%} anchors, eps {r['eps']}, {r['outer_iters']} outer x "
+             f"{r['inner_iters']} inner iterations; times are HIP events around fa_align with inputs resident.",
+             "",
+             "| n | form | plan in C^T | align s | inner iterations | final L1 error | Hits@1 | Hits@10 | MRR | device GB |",
+             "|---:|---|---|---:|---:|---:|---:|---:|---:|---:|"]
+    for x in out["rows"]:
+        lines.append(f"| {x['n']} | {x['form']} | {'yes' if x['plan_in_ct'] else 'no'} | {x['align_s']:.3f} | "
+                     f"{x['inner_total']} | {x['marg_err']:.2e} | {x['hits_at_1']:.4f} | {x['hits_at_10']:.4f} | "
+                     f"{x['mrr']:.4f} | {x['device_gb']:.1f} |")
+    lines += ["", f"Device memory {out['device_memory_bytes'] / 1e9:.1f} GB; largest n of this recipe that fits "
+                  f"(97% of it, the library's workspace query): " +
+              ", ".join(f"{k} {v}" for k, v in out["largest_n_that_fits"].items()),
+              f"", f"Sweep wall time {out.get('seconds', 0):.0f} s.", ""]
+    return "\n".join(lines)
 
 
 if __name__ == "__main__":
