@@ -8,7 +8,8 @@ A step is one outer iteration of Algorithm 1 on resident state (cost rebuild fro
 the sparse adjacencies and the dense plan, the inner Sinkhorn solve, the plan),
 called through the C ABI (fa_align_step).  The headline form (plan in BF16, FP32
 cost and SpMM intermediates, FP64 duals, learned warm start of the first solve
-when trained weights are present with the cold rerun as its fallback, later solves
+when trained weights are present (50 iterations, then the cold rerun as its
+fallback when it has not met the tolerance), later solves
 started from the mean of the earlier solves' duals) runs
 ONE alignment: fa_align_begin (Phase 1), then outer iterations 0..T-1 as steps
 (the first W are the untimed warm-up, the next K are timed together), then
@@ -61,6 +62,8 @@ def parse():
     ap.add_argument("--cold", action="store_true", help="headline form without the learned warm start")
     ap.add_argument("--start", default="mean", choices=["zero", "carry", "mean"],
                     help="headline form: start of the inner solves after the first")
+    ap.add_argument("--warm-probe", type=int, default=50,
+                    help="iterations granted to the learned start before its cold rerun (0: the whole solve)")
     ap.add_argument("--no-f32-mean", action="store_true",
                     help="skip the FP32 run with the headline's start policy (the precision-only comparison)")
     ap.add_argument("--plan-in-ct", action="store_true",
@@ -70,6 +73,11 @@ def parse():
     ap.add_argument("--cpu-workers", type=int, default=0, help="oracle processes for the CPU baseline (0: all)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one 4 GiB device-to-device copy first (reference for HBM byte counters)")
+    ap.add_argument("--ingest-counters", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="no GPU run: read two rocprofv3 --pmc csv outputs (FETCH_SIZE, WRITE_SIZE) of "
+                         "`bench.py --outer 1 --steps 1 --warmup 0 --no-plain --no-f32-mean --no-cpu "
+                         "--calibrate-copy` and write the per-launch HBM bytes of the headline form's kernels "
+                         "into profiles/traffic.json (printing a markdown table)")
     return ap.parse_args()
 
 
@@ -165,8 +173,84 @@ def kernel_table(st, pair, nnz1, nnz2, p, binding):
     return out
 
 
+# kernel class of the headline form -> the kernel's name prefix in a rocprofv3 record
+KERNEL_NAMES = {"lse_col_t": "fa::k_lse_col_t<4, 8>", "lse_row": "fa::k_lse_row<4, 8>",
+                "cost_stage1": "fa::k_stage1<unsigned short, true, 2, 8, true>",
+                "cost_stage2": "fa::k_stage2<true, true>", "plan": "fa::k_plan<4, unsigned short>",
+                "featsim": "fa::k_featsim_bf16"}
+
+
+def _counter_rows(d):
+    """(kernel name, grid size, counter value) per dispatch from a rocprofv3 csv output tree."""
+    import csv
+    import glob
+    files = glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)
+    if not files:
+        raise SystemExit(f"no *counter_collection.csv under {d}")
+    per = {}
+    for f in files:
+        with open(f, newline="") as fh:
+            for r in csv.DictReader(fh):
+                key = (f, r.get("Dispatch_Id") or r.get("Correlation_Id"))
+                name = r["Kernel_Name"]
+                ent = per.setdefault(key, [name, int(r.get("Grid_Size", 0) or 0), 0.0])
+                ent[2] += float(r["Counter_Value"])
+    return list(per.values())
+
+
+def ingest_counters(fetch_dir, write_dir, workload="cl120k:120000x120000"):
+    """FETCH_SIZE and WRITE_SIZE (KiB per dispatch) of one outer iteration of the headline
+    form, scaled by what the same counters read for the run's 4 GiB device-to-device copy
+    (--calibrate-copy), averaged per kernel class -> profiles/traffic.json."""
+    fetch, write = _counter_rows(fetch_dir), _counter_rows(write_dir)
+    copy_bytes = 4.0 * 2**30
+
+    def calib(rows):
+        vals = [v for name, _, v in rows if "copyBuffer" in name or "copy" in name.lower()]
+        if not vals:
+            raise SystemExit("no copy kernel in the counter record (run with --calibrate-copy)")
+        return copy_bytes / (max(vals) * 1024.0)
+
+    ff, wf = calib(fetch), calib(write)
+
+    def per_kernel(rows, factor, prefix):
+        # the runtime warm-up pair (200 nodes) dispatches the same kernels with tiny grids: keep the big ones
+        vals = [(g, v) for name, g, v in rows if name.startswith(prefix)]
+        if not vals:
+            return None, 0
+        gmax = max(g for g, _ in vals)
+        big = [v for g, v in vals if g * 8 >= gmax]
+        return sum(big) / len(big) * 1024.0 * factor, len(big)
+
+    rec = dict(calibration=dict(fetch_factor=ff, write_factor=wf, reference="4 GiB device-to-device copy"),
+               kernels={})
+    lines = ["| kernel | launches | read GB/launch | written GB/launch | total GB/launch | algorithmic GB | ratio |",
+             "|---|---:|---:|---:|---:|---:|---:|"]
+    import math as _m
+    n = 120000
+    chunk = n / _m.ceil(n / n_chunk(n, n, 4))
+    for kind, prefix in KERNEL_NAMES.items():
+        fb, nl = per_kernel(fetch, ff, prefix)
+        wb, _ = per_kernel(write, wf, prefix)
+        if fb is None or wb is None:
+            continue
+        alg = algorithmic_bytes(kind, n, n, 0, 0, chunk, 2, 6)
+        rec["kernels"][kind] = dict(workload=workload, kernel=prefix, launches=nl, bytes_per_launch=fb + wb,
+                                    fetch_bytes=fb, write_bytes=wb, algorithmic_bytes=alg,
+                                    source_digest=source_digest(kind))
+        lines.append(f"| `{prefix}` | {nl} | {fb / 1e9:.2f} | {wb / 1e9:.2f} | {(fb + wb) / 1e9:.2f} | "
+                     f"{alg / 1e9:.2f} | {(fb + wb) / alg:.2f} |")
+    with open(TRAFFIC, "w") as f:
+        json.dump(rec, f, indent=1)
+    print(f"calibration: FETCH_SIZE x {ff:.4f}, WRITE_SIZE x {wf:.4f}")
+    print("\n".join(lines))
+
+
 def main():
     args = parse()
+    if args.ingest_counters:
+        ingest_counters(*args.ingest_counters)
+        return
     if args.gpus != 1:
         print(f"bench.py runs on exactly one GPU in this build (asked for {args.gpus}); "
               "multi-GPU sharding is designed but not built.", file=sys.stderr)
@@ -209,7 +293,7 @@ def main():
     # top-2 lists of the final plan give each row's margin log(S_top / S_second)
     lean = dict(topk=10, dense_plan=False) if args.plan_in_ct else dict(topk=2)
     p_head = api.params(plan_dtype="bf16", feat_dtype="bf16", warm_start=mlp is not None, dual_start=args.start,
-                        **common)
+                        warm_probe=args.warm_probe, **common)
     p_plain = api.params(plan_dtype="f32", feat_dtype="f32", warm_start=False, dual_start="zero", **common)
     p_f32s = api.params(plan_dtype="f32", feat_dtype="f32", warm_start=False, dual_start=args.start, **common)
 
@@ -250,12 +334,13 @@ def main():
         f"warm start {mlp is not None}, later solves start {args.start}")
     n_outer = max(T, W + K)   # steps past T (only when W + K > T) continue the same iteration
     acc = binding.fa_stats()
+    p1 = binding.fa_stats()
     torch.cuda.synchronize()
     e_all0, e_all1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e_k0, e_k1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e_T = torch.cuda.Event(enable_timing=True)
     e_all0.record()
-    al.begin()
+    al.begin(p1)
     for t in range(n_outer):
         if t == W:
             torch.cuda.synchronize()
@@ -278,6 +363,7 @@ def main():
                 ms_per_outer_timed=ms_step, **solve_summary(res.stats, n_outer),
                 kernels_timed_steps=kernel_table(acc, pair, inp.A1.nnz, inp.A2.nnz, p_head, binding),
                 phase_ms_timed_steps=dict(cost=acc.phase_ms[1], sinkhorn=acc.phase_ms[2], plan=acc.phase_ms[3]),
+                phase1_ms=p1.phase_ms[0], kernels_phase1=kernel_table(p1, pair, inp.A1.nnz, inp.A2.nnz, p_head, binding),
                 status=int(res.status))
     if n_outer != T:
         head["note"] = f"{n_outer} outer iterations ran; align_s covers Phase 1 and the first {T}"
@@ -366,7 +452,8 @@ def main():
                             n1=pair.n1, n2=pair.n2, outer_iters=T, inner_cap=cfg.inner_iters, tol=1e-6,
                             step="one outer iteration (cost rebuild + inner solve + plan) of the headline form",
                             value="device time of the whole headline alignment (Phase 1 + all outer iterations)"),
-                warm_start=mlp is not None, dual_start=args.start, plan_in_ct=args.plan_in_ct, headline=head,
+                warm_start=mlp is not None, warm_probe=args.warm_probe, dual_start=args.start,
+                plan_in_ct=args.plan_in_ct, headline=head,
                 plain_fp32=plain, fp32_same_start=f32s, argmax_agreement=agree,
                 speedup_vs_plain=(plain["align_s"] / head["align_s"] if plain else None),
                 spmm_gbps=spmm, roofline=roofline, cpu_baseline=cpu, skipped=skipped,

@@ -102,6 +102,11 @@ typedef struct {
                          learned duals misses tol, the same solve is rerun from a = b = 0 and
                          the run keeps whichever ends with the smaller marginal error
                          (fa_stats.fell_back = 2 when the cold solve is kept) */
+  int32_t warm_probe; /* with warm_fallback and tol > 0: iterations granted to the solve from
+                         the learned duals before the cold rerun takes over (0: inner_iters).
+                         A learned start either
+                         converges within a few dozen iterations or decays at the cold rate,
+                         so a short probe bounds what a miss costs. */
 } fa_params;
 
 /* Starts of the inner solves after the first (fa_params.dual_start). */
@@ -347,6 +352,8 @@ int fa_align(const fa_csr *A1, const fa_csr *A2, const float *X1, const float *X
  *
  * fa_align_begin: anchor check (synchronises once), Phase 1, S^0 = mu nu^T in the
  *   working plan (S_out, or the C^T buffer with p->plan_in_ct), warm-start inputs.
+ *   acc (host, nullable): phase_ms[0] accumulates the call's device time and, with
+ *   p->profile, kernel_ms / kernel_calls its launches (the similarity GEMM).
  * fa_align_step: outer iteration t (cost rebuild, inner solve from the start the
  *   params select, plan).  argmax_out/truth/rank_out (nullable; truth and rank_out
  *   together) are written from this step's plan, as fa_align does on its last step.
@@ -360,7 +367,7 @@ int fa_align(const fa_csr *A1, const fa_csr *A2, const float *X1, const float *X
  *   FA_WARN_NOT_CONVERGED like fa_align. */
 int fa_align_begin(const fa_csr *A1, const fa_csr *A2, const float *X1, const float *X2, int32_t d,
                    const int32_t *anchors, int32_t nL, const fa_params *p, void *S_out, double *a_out,
-                   double *b_out, void *ws, size_t ws_bytes, void *stream);
+                   double *b_out, fa_stats *acc, void *ws, size_t ws_bytes, void *stream);
 int fa_align_step(const fa_csr *A1, const fa_csr *A2, int32_t d, int32_t nL, const fa_params *p,
                   const float *mlp_weights, int32_t t, void *S_out, double *a_out, double *b_out,
                   int32_t *argmax_out, const int32_t *truth, int32_t *rank_out, fa_stats *acc, void *ws,

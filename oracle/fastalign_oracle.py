@@ -45,9 +45,11 @@ with their reasons in the design notes of the repository):
       reaches the same optimum from any start (its duals are unique up to a
       constant shift that the plan and the cost update do not see), so the
       variants change only iterates that stop before convergence.
-* R17 A learned start (b_init) of the first solve whose solve misses tol is
-      rerun from zero duals, and the run keeps whichever of the two solves ends
-      with the smaller marginal error (the cold start stays the reference).
+* R17 With the fallback on and tol > 0, a learned start (b_init) of the first
+      solve gets warm_probe iterations (0: the full inner budget); if that solve
+      misses tol, the solve is rerun from
+      zero duals with the full budget, and the run keeps whichever of the two solves
+      ends with the smaller marginal error (the cold start stays the reference).
 """
 from __future__ import annotations
 
@@ -86,6 +88,7 @@ class Params:
     feat_l2norm: bool = True
     dual_start: str = "zero"             # R14: "zero", "carry" or "mean" start of the solves after the first
     warm_fallback: bool = True           # R17: rerun a learned start's solve cold when it misses tol
+    warm_probe: int = 0                  # R17: iterations granted to the learned start (0: inner_iters)
 
     @property
     def lp(self) -> float:
@@ -346,7 +349,10 @@ def align(n1, rowptr1, colidx1, n2, rowptr2, colidx2, X1, X2, anchors, p: Params
         elif t > 0 and p.dual_start == "mean":
             a0 = sum(solved_a) / len(solved_a)
             b0 = sum(solved_b) / len(solved_b)
-        a, b, it, err = sinkhorn(C, p.eps, p.inner_iters, p.tol, a0, b0)
+        budget = p.inner_iters
+        if t == 0 and b_init is not None and p.warm_fallback and p.tol > 0 and p.warm_probe > 0:
+            budget = min(p.warm_probe, p.inner_iters)
+        a, b, it, err = sinkhorn(C, p.eps, budget, p.tol, a0, b0)
         if t == 0 and b_init is not None:
             warm.update(warm_iters=it, warm_err=err)
             if p.warm_fallback and p.tol > 0 and not err <= p.tol:

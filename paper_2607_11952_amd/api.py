@@ -91,7 +91,7 @@ def params(**kw) -> B.fa_params:
         if k == "dual_start" and isinstance(v, str):
             v = {"zero": B.FA_START_ZERO, "carry": B.FA_START_CARRY, "mean": B.FA_START_MEAN}[v]
         if k in ("feat_l2norm", "warm_start", "profile", "dual_start", "transpose_cost", "plan_in_ct",
-                 "warm_fallback"):
+                 "warm_fallback", "warm_probe"):
             v = int(v)
         setattr(p, k, v)
     if "lambda_p" not in kw:
@@ -278,12 +278,14 @@ class Aligner:
         return (C.byref(inp.A1.c), C.byref(inp.A2.c), int(inp.X1.shape[1]), int(inp.anchors.shape[0]),
                 C.byref(self.p))
 
-    def begin(self):
-        """Phase 1 and S^0 (synchronises once for the anchor check)."""
+    def begin(self, acc: Optional[B.fa_stats] = None):
+        """Phase 1 and S^0 (synchronises for the anchor check and at the end); acc receives
+        its device time (phase_ms[0]) and, with p.profile, its kernels' timings."""
         inp = self.inp
         _lib().call("fa_align_begin", C.byref(inp.A1.c), C.byref(inp.A2.c), _ptr(inp.X1), _ptr(inp.X2),
                     int(inp.X1.shape[1]), _ptr(inp.anchors), int(inp.anchors.shape[0]), C.byref(self.p),
-                    _ptr(self.S), _ptr(self.a), _ptr(self.b), _ptr(self.ws), self.ws_bytes, _stream())
+                    _ptr(self.S), _ptr(self.a), _ptr(self.b), C.byref(acc) if acc is not None else None,
+                    _ptr(self.ws), self.ws_bytes, _stream())
 
     def step(self, t: int, last: bool = False, acc: Optional[B.fa_stats] = None):
         """Outer iteration t; with last=True its plan pass also writes argmax (and ranks)."""

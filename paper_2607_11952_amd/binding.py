@@ -47,6 +47,7 @@ class fa_params(C.Structure):
         ("transpose_cost", C.c_int32),
         ("plan_in_ct", C.c_int32),
         ("warm_fallback", C.c_int32),
+        ("warm_probe", C.c_int32),
     ]
 
 
@@ -92,7 +93,7 @@ _SIGS = {
     "fa_align": (C.c_int, [C.POINTER(fa_csr), C.POINTER(fa_csr), _P, _P, _I32, _P, _I32, C.POINTER(fa_params),
                            _P, _P, _P, _P, _P, _P, _P, _I32, _P, _P, C.POINTER(fa_stats), _P, _SZ, _P]),
     "fa_align_begin": (C.c_int, [C.POINTER(fa_csr), C.POINTER(fa_csr), _P, _P, _I32, _P, _I32,
-                                 C.POINTER(fa_params), _P, _P, _P, _P, _SZ, _P]),
+                                 C.POINTER(fa_params), _P, _P, _P, C.POINTER(fa_stats), _P, _SZ, _P]),
     "fa_align_step": (C.c_int, [C.POINTER(fa_csr), C.POINTER(fa_csr), _I32, _I32, C.POINTER(fa_params), _P, _I32,
                                 _P, _P, _P, _P, _P, _P, C.POINTER(fa_stats), _P, _SZ, _P]),
     "fa_align_end": (C.c_int, [C.POINTER(fa_csr), C.POINTER(fa_csr), _I32, _I32, C.POINTER(fa_params), _I32, _P, _P,

@@ -191,6 +191,7 @@ static int validate(const fa_csr *A1, const fa_csr *A2, int32_t d, int32_t nL, c
              p->feat_dtype);
   FA_REQUIRE(p->dual_start == FA_START_ZERO || p->dual_start == FA_START_CARRY || p->dual_start == FA_START_MEAN,
              FA_ERR_ARG, "fa_align: dual_start %d", p->dual_start);
+  FA_REQUIRE(p->warm_probe >= 0, FA_ERR_ARG, "fa_align: warm_probe %d < 0", p->warm_probe);
   FA_REQUIRE(!p->plan_in_ct || p->transpose_cost, FA_ERR_ARG, "fa_align: plan_in_ct needs transpose_cost = 1");
   return FA_OK;
 }
@@ -363,8 +364,10 @@ static int align_step(AlignCtx &x, int32_t t, const float *mlp, void *S_out, dou
   int32_t *it_slot = B.st_iters + slot;
   double *er_slot = B.st_err + slot;
   const float *Ct = p->transpose_cost ? B.Ct : nullptr;
-  FA_TRY(run_sinkhorn(B.C, Ct, n1, n2, p->eps, a, b, p->inner_iters, p->tol, p->check_every, it_slot, er_slot, B.sink,
-                      s, tm));
+  // the learned start's solve gets warm_probe iterations when a cold rerun backs it up
+  const bool probe = warm && p->warm_fallback && p->tol > 0 && p->warm_probe > 0 && p->warm_probe < p->inner_iters;
+  const int32_t budget = probe ? p->warm_probe : p->inner_iters;
+  FA_TRY(run_sinkhorn(B.C, Ct, n1, n2, p->eps, a, b, budget, p->tol, p->check_every, it_slot, er_slot, B.sink, s, tm));
   if (warm) {
     // The cold start stays the reference: a learned start whose solve misses tol is
     // rerun from zero duals and the run keeps whichever solve ends closer to the
@@ -547,10 +550,43 @@ extern "C" int fa_align(const fa_csr *A1, const fa_csr *A2, const float *X1, con
 
 extern "C" int fa_align_begin(const fa_csr *A1, const fa_csr *A2, const float *X1, const float *X2, int32_t d,
                               const int32_t *anchors, int32_t nL, const fa_params *p, void *S_out, double *a_out,
-                              double *b_out, void *ws, size_t ws_bytes, void *stream) {
+                              double *b_out, fa_stats *acc, void *ws, size_t ws_bytes, void *stream) {
   AlignCtx x;
   FA_TRY(open_ctx(x, A1, A2, d, nL, p, ws, ws_bytes, stream));
-  return align_begin(x, X1, X2, anchors, S_out, a_out, b_out, nullptr);
+  KTimer *tm = nullptr;
+  struct TmGuard {
+    KTimer *&t;
+    ~TmGuard() { delete t; }
+  } tmguard{tm};
+  if (p->profile && acc) {
+    tm = new KTimer();
+    FA_REQUIRE(tm->init(), FA_ERR_HIP, "fa_align_begin: could not create timing events");
+  }
+  hipEvent_t e0, e1;
+  FA_HIP(hipEventCreate(&e0));
+  struct EvGuard {
+    hipEvent_t a, b;
+    bool hb;
+    ~EvGuard() {
+      (void)hipEventDestroy(a);
+      if (hb) (void)hipEventDestroy(b);
+    }
+  } evg{e0, e0, false};
+  FA_HIP(hipEventCreate(&e1));
+  evg.b = e1;
+  evg.hb = true;
+  FA_HIP(hipEventRecord(e0, x.s));
+  FA_TRY(align_begin(x, X1, X2, anchors, S_out, a_out, b_out, tm));
+  FA_HIP(hipEventRecord(e1, x.s));
+  FA_HIP(hipEventSynchronize(e1));
+  if (acc) {
+    float f = 0.f;
+    FA_HIP(hipEventElapsedTime(&f, e0, e1));
+    const double phase_ms[4] = {f, 0.0, 0.0, 0.0};
+    if (tm) tm->collect();
+    stats_timing(acc, tm, phase_ms, true);
+  }
+  return FA_OK;
 }
 
 extern "C" int fa_align_step(const fa_csr *A1, const fa_csr *A2, int32_t d, int32_t nL, const fa_params *p,

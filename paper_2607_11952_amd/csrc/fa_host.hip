@@ -51,6 +51,7 @@ extern "C" void fa_default_params(fa_params *p) {
   p->transpose_cost = 1;
   p->plan_in_ct = 0;
   p->warm_fallback = 1;
+  p->warm_probe = 0;
 }
 
 extern "C" int fa_device_check(void) {

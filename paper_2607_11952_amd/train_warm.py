@@ -47,11 +47,12 @@ def family(seed: int, n: int = 0):
         eps=EPS)
 
 
-def first_solve(inp, inner: int, mlp=None, tol: float = 0.0, fallback: bool = False):
+def first_solve(inp, inner: int, mlp=None, tol: float = 0.0, fallback: bool = False, probe: int = 0):
     """One outer iteration (the first inner solve); with a network, the learned start
-    alone (fallback False) or with the library's cold rerun when it misses tol."""
+    alone (fallback False) or with the library's cold rerun when it misses tol within
+    `probe` iterations (0: the whole budget)."""
     p = api.params(eps=EPS, outer_iters=1, inner_iters=inner, tol=tol, warm_start=mlp is not None,
-                   warm_fallback=int(fallback))
+                   warm_fallback=int(fallback), warm_probe=probe)
     return api.align(inp, p, mlp=mlp)
 
 
@@ -107,7 +108,8 @@ def train(F: torch.Tensor, t: torch.Tensor, epochs: int, batch: int, lr: float, 
     return prm, hist
 
 
-def evaluate(prm: torch.Tensor, seeds, n: int, K: int, device, log=print, tol: float = 1e-6, cap: int = 1000):
+def evaluate(prm: torch.Tensor, seeds, n: int, K: int, device, log=print, tol: float = 1e-6, cap: int = 1000,
+             probe: int = 0):
     rows = []
     for s in seeds:
         pr = make_pair(family(s, n))
@@ -125,13 +127,13 @@ def evaluate(prm: torch.Tensor, seeds, n: int, K: int, device, log=print, tol: f
         wt_it, wt_err = int(wt.stats.inner_iters[0]), float(wt.stats.inner_err[0])
         agree_tol = float((wt.argmax == ct_arg).float().mean())
         # the product path: learned start, cold rerun when it misses tol (both solves counted)
-        fb = first_solve(inp, cap, mlp=prm, tol=tol, fallback=True)
+        fb = first_solve(inp, cap, mlp=prm, tol=tol, fallback=True, probe=probe)
         fb_it, fb_err, fb_fell = int(fb.stats.inner_iters[0]), float(fb.stats.inner_err[0]), int(fb.stats.fell_back)
         agree_fb = float((fb.argmax == ct_arg).float().mean())
         rows.append(dict(seed=s, n=n, K=K, err_cold=e_cold, err_warm=e_warm, iters_warm_to_cold_err=it_warm,
                          argmax_agreement=agree, tol=tol, cap=cap, iters_cold_to_tol=ct_it, err_cold_at_stop=ct_err,
                          iters_warm_to_tol=wt_it, err_warm_at_stop=wt_err, argmax_agreement_at_tol=agree_tol,
-                         iters_fallback=fb_it, err_fallback=fb_err, fell_back=fb_fell,
+                         probe=probe, iters_fallback=fb_it, err_fallback=fb_err, fell_back=fb_fell,
                          argmax_agreement_fallback=agree_fb))
         log(f"[eval] seed {s}: err after {K}: cold {e_cold:.3e} warm {e_warm:.3e}; warm reaches the cold error in "
             f"{it_warm} iterations; argmax agreement {agree:.4f}; to {tol:g}: cold {ct_it} ({ct_err:.2e}) "
@@ -161,6 +163,43 @@ def summarize(rows):
                 min_argmax_agreement_fallback=float(np.min(f("argmax_agreement_fallback"))))
 
 
+def markdown(rows, summ, argv: str) -> str:
+    """The held-out evaluation as a short markdown record (summary + per-pair table)."""
+    r0 = rows[0]
+    out = ["# Learned warm start on held-out pairs of its family",
+           "",
+           f"Command (repository root): `python -m paper_2607_11952_amd.train_warm {argv}`",
+           "",
+           f"{summ['pairs']} pairs at n = {r0['n']} (seeds {rows[0]['seed']}..{rows[-1]['seed']}, outside the "
+           f"training seeds), first inner solve, eps {EPS}; tolerance {r0['tol']:g} with a cap of {r0['cap']} "
+           f"iterations; the product path gives the learned start {r0.get('probe', 0) or r0['cap']} iterations, then the "
+           f"cold rerun when it has not met the tolerance.",
+           "",
+           "| | cold start | learned start alone | learned start + cold fallback |",
+           "|---|---:|---:|---:|",
+           f"| mean iterations (to tol or cap) | {summ['mean_iters_cold_to_tol']:.1f} | {summ['mean_iters_warm_to_tol']:.1f} "
+           f"| {summ['mean_iters_fallback']:.1f} |",
+           f"| pairs reaching tol | {summ['cold_reached_tol']} | {summ['warm_reached_tol']} | "
+           f"{summ['fallback_reached_tol']} |",
+           f"| iteration ratio cold / this | 1 | {summ['iteration_ratio']:.2f} | "
+           f"{summ['iteration_ratio_with_fallback']:.2f} |",
+           f"| min / mean argmax agreement with cold at the stop | - | {summ['min_argmax_agreement_at_tol']:.4f} / "
+           f"{summ['mean_argmax_agreement_at_tol']:.4f} | {summ['min_argmax_agreement_fallback']:.4f} |",
+           "",
+           f"After K = {r0['K']} iterations: mean error cold {summ['mean_err_cold']:.3e}, learned "
+           f"{summ['mean_err_warm']:.3e}, median ratio {summ['median_err_ratio']:.1f}; the learned start reaches "
+           f"the cold K-iteration error in {summ['mean_iters_warm_to_cold_err']:.1f} iterations on average "
+           f"({summ['speedup_to_cold_err']:.2f}x fewer).  Cold rerun used in {summ['fell_back_pairs']} pairs.",
+           "",
+           "| seed | cold it | cold err | learned it | learned err | +fallback it | +fallback err | kept |",
+           "|---:|---:|---:|---:|---:|---:|---:|---|"]
+    for r in rows:
+        out.append(f"| {r['seed']} | {r['iters_cold_to_tol']} | {r['err_cold_at_stop']:.2e} | {r['iters_warm_to_tol']} "
+                   f"| {r['err_warm_at_stop']:.2e} | {r['iters_fallback']} | {r['err_fallback']:.2e} | "
+                   f"{'cold' if r['fell_back'] else 'learned'} |")
+    return "\n".join(out) + "\n"
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--pairs", type=int, default=2000)
@@ -174,18 +213,39 @@ def main():
     ap.add_argument("--eval-seed0", type=int, default=5000)
     ap.add_argument("--tol", type=float, default=1e-6)
     ap.add_argument("--cap", type=int, default=1000)
+    ap.add_argument("--probe", type=int, default=50,
+                    help="iterations granted to the learned start before the cold rerun (0: the cap)")
     ap.add_argument("--out", default=warm.WEIGHTS)
     ap.add_argument("--report", default="")
+    ap.add_argument("--md", default="", help="markdown record of the evaluation")
+    ap.add_argument("--merge", nargs="*", default=None,
+                    help="no GPU: merge the eval rows of these report files into one summary (--md / --report)")
     ap.add_argument("--eval-only", action="store_true", help="evaluate --weights, no training")
     ap.add_argument("--weights", default=warm.WEIGHTS)
     args = ap.parse_args()
+    if args.merge:
+        rows = []
+        for f in args.merge:
+            with open(f) as fh:
+                rows += json.load(fh)["eval"]
+        rows.sort(key=lambda r: r["seed"])
+        summ = summarize(rows)
+        if args.md:
+            with open(args.md, "w") as fh:
+                fh.write(markdown(rows, summ, " ".join(sys.argv[1:])))
+        if args.report:
+            with open(args.report, "w") as fh:
+                json.dump(dict(eval=rows, summary=summ), fh, indent=1)
+        print(json.dumps(summ))
+        return
     dev = torch.device("cuda:0")
     log = lambda m: print(m, file=sys.stderr, flush=True)
     t0 = time.time()
     seeds = range(args.eval_seed0, args.eval_seed0 + args.eval_pairs)
     if args.eval_only:
         prm = torch.from_numpy(warm.read_weights(args.weights)).to(dev)
-        rows = evaluate(prm, seeds, args.eval_n, args.eval_k, dev, log=log, tol=args.tol, cap=args.cap)
+        rows = evaluate(prm, seeds, args.eval_n, args.eval_k, dev, log=log, tol=args.tol, cap=args.cap,
+                        probe=args.probe)
         summ = summarize(rows)
         if args.report:
             with open(args.report, "w") as f:
@@ -207,7 +267,8 @@ def main():
     prm, hist = train(F, t, args.epochs, args.batch, args.lr, log=log)
     warm.save_weights(prm.cpu().numpy(), args.out)
     log(f"[train] saved {args.out}")
-    rows = evaluate(prm, seeds, args.eval_n, args.eval_k, dev, log=log, tol=args.tol, cap=args.cap)
+    rows = evaluate(prm, seeds, args.eval_n, args.eval_k, dev, log=log, tol=args.tol, cap=args.cap,
+                    probe=args.probe)
     summ = summarize(rows)
     rep = dict(pairs=args.pairs, nodes=int(F.shape[0]), target_var=float(t.var()), mse_per_epoch=hist,
                eval=rows, summary=summ, seconds=time.time() - t0)

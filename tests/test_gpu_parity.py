@@ -139,16 +139,19 @@ def test_feature_sim_fp32(api, shape):
     assert np.allclose(got, want, rtol=2e-6, atol=2e-6)
 
 
-@pytest.mark.parametrize("shape", [(300, 260, 64, 45), (257, 300, 136, 72), (130, 129, 7, 200)])
+@pytest.mark.parametrize("shape", [(300, 260, 64, 45), (257, 300, 136, 72), (130, 129, 7, 200),
+                                   (600, 520, 128, 120), (513, 129, 0, 40), (256, 128, 24, 0)])
 def test_feature_sim_bf16(api, shape):
-    """K across several 64-element steps, vector (K*2 a multiple of 16) and element staging."""
+    """256 x 128 tiles with ragged edges in both dimensions, several tiles each way;
+    K across several 64-element steps (one to four double-buffered stages), vector
+    (K*2 a multiple of 16) and element staging; either product absent."""
     n1, n2, d, nL = shape
     r = np.random.default_rng(5)
     X1, X2 = r.standard_normal((n1, d)), r.standard_normal((n2, d))
     R1, R2 = r.random((n1, nL)) * 0.3, r.random((n2, nL)) * 0.3
     t = lambda a: torch.from_numpy(np.ascontiguousarray(a, np.float32)).cuda()
-    Xh1 = api.l2_normalize(t(X1), torch.bfloat16)
-    Xh2 = api.l2_normalize(t(X2), torch.bfloat16)
+    Xh1 = api.l2_normalize(t(X1), torch.bfloat16) if d else t(X1).to(torch.bfloat16)
+    Xh2 = api.l2_normalize(t(X2), torch.bfloat16) if d else t(X2).to(torch.bfloat16)
     Rb1, Rb2 = t(R1).to(torch.bfloat16), t(R2).to(torch.bfloat16)
     got = _np(api.feature_sim(Xh1, Xh2, Rb1, Rb2, 0.5))
     # reference: the same BF16-rounded operands in FP64 (products are exact in FP32 accumulation up to ~1e-6)

@@ -515,3 +515,31 @@ def test_plan_topk_vs_library_sort_and_stable_brute_force():
         for i in range(n1):
             want = sorted(range(n2), key=lambda j: -St[i, j])[:k]   # stable: lower j first on ties
             assert list(idx[i]) == want
+
+
+@pytest.mark.parametrize("probe", [0, 7])
+def test_learned_start_fallback_rule(probe):
+    """R17 on the oracle: a learned start whose solve (probe iterations, or the full
+    budget with probe 0) misses tol is rerun cold with the full budget; when the cold
+    solve ends closer, the run is the cold run itself (plan bit for bit) and both
+    solves' iterations count; a start that meets tol is kept with no rerun."""
+    import dataclasses
+    n = 30
+    e1, e2, X1, X2, L, pi = _small_pair(n=n, seed=35, anchors=3, noise=0.3)
+    p = O.Params(eps=0.1, outer_iters=2, inner_iters=20, tol=1e-12, warm_probe=probe)
+    cold = _run(n, e1, n, e2, X1, X2, L, p)
+    bad = np.random.default_rng(3).standard_normal(n) * 50.0          # far from any solution
+    with np.errstate(over="ignore"):   # the marginal error of the far start itself overflows
+        got = _run(n, e1, n, e2, X1, X2, L, p, b_init=bad)
+    budget = probe if probe else p.inner_iters
+    assert got["warm_iters"] == budget and got["cold_iters"] == p.inner_iters
+    assert got["fell_back"] == 2 and got["warm_err"] > got["cold_err"]
+    assert got["iters"][0] == budget + p.inner_iters and got["iters"][1:] == cold["iters"][1:]
+    assert np.array_equal(got["S"], cold["S"])
+    # a start that meets the tolerance is kept: the converged duals of the first solve
+    # (eps 0.3 and lambda_n = 0 keep the kernel's range small enough to converge to 1e-9)
+    p2 = dataclasses.replace(p, eps=0.3, tol=1e-9, inner_iters=5000, lambda_n=0.0)
+    ref = _run(n, e1, n, e2, X1, X2, L, dataclasses.replace(p2, outer_iters=1))
+    good = _run(n, e1, n, e2, X1, X2, L, p2, b_init=ref["b"])
+    assert good["fell_back"] == 0 and good["cold_iters"] == -1 and good["warm_err"] <= 1e-9
+    assert good["iters"][0] == good["warm_iters"] <= 2
