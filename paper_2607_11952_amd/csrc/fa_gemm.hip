@@ -194,161 +194,6 @@ __global__ __launch_bounds__(256) void k_featsim(const TX *__restrict__ X1, cons
     }
 }
 
-// ---------------------------------------------------------------- BF16 x BF16
-// With both operands BF16 a 64 x 64 wave tile is bound by LDS bandwidth, not by
-// the matrix cores: per 16-wide K step a wave reads four 1 KB fragments from LDS
-// for four 32x32x16 MFMAs (32 KB of fragment reads and 8 KB of staging writes per
-// CU for 16 MFMAs of 32 cycles each: 192 LDS cycles against 128 MFMA cycles).
-// This kernel gives each wave 128 x 64 (4 x 2 blocks: six fragments for eight
-// MFMAs) and each workgroup 256 x 128, with both accumulator sets in the matrix
-// accumulators (256 per lane, one wave per SIMD), double-buffered LDS stages (one
-// barrier per 64-element K step) and the next step's global loads in flight
-// during the current step's MFMAs.
-constexpr int kTileM2 = 256, kTileN2 = 128;
-constexpr int kStageA2 = kTileM2 * kLdsRow, kStageB2 = kTileN2 * kLdsRow;
-
-// Rows [row0, row0+ROWS) x K elements [k0, k0+64) of a row-major [rows x K] BF16
-// operand, ROWS * 8 pieces of 16 bytes, ROWS / 32 per thread; out of range = 0.
-template <int ROWS>
-__device__ inline void load_panel(const uint16_t *__restrict__ M, int32_t rows, int32_t K, int row0, int k0, bool vec,
-                                  uint4 (&v)[ROWS / 32]) {
-#pragma unroll
-  for (int i = 0; i < ROWS / 32; ++i) {
-    const int q = threadIdx.x + 256 * i;
-    const int r = q >> 3, piece = q & 7;
-    const int grow = row0 + r, gk = k0 + piece * 8;
-    uint4 x = make_uint4(0u, 0u, 0u, 0u);
-    if (grow < rows && gk < K) {
-      const uint16_t *p = M + static_cast<int64_t>(grow) * K + gk;
-      if (vec) {
-        x = *reinterpret_cast<const uint4 *>(p);
-      } else {
-        uint16_t e[8];
-#pragma unroll
-        for (int t = 0; t < 8; ++t) e[t] = gk + t < K ? p[t] : uint16_t(0);
-        __builtin_memcpy(&x, e, 16);
-      }
-    }
-    v[i] = x;
-  }
-}
-
-template <int ROWS>
-__device__ inline void store_panel(const uint4 (&v)[ROWS / 32], uint8_t *__restrict__ lds) {
-#pragma unroll
-  for (int i = 0; i < ROWS / 32; ++i) {
-    const int q = threadIdx.x + 256 * i;
-    *reinterpret_cast<uint4 *>(lds + (q >> 3) * kLdsRow + (q & 7) * 16) = v[i];
-  }
-}
-
-// One staged 64-element K step for a wave's 128 x 64 block: lane l supplies
-// A[m = l%32][k = 8(l/32) .. +8] and the same slice of B (one 16-byte LDS read each).
-__device__ inline void mma_stage_bf16(const uint8_t *__restrict__ la, const uint8_t *__restrict__ lb, int wm, int wn,
-                                      int lane, floatx16 (&acc)[4][2]) {
-  const int half = lane >> 5, r = lane & 31;
-#pragma unroll
-  for (int ks = 0; ks < kChunkBytes / 32; ++ks) {
-    bf16x8 av[4], bv[2];
-#pragma unroll
-    for (int p = 0; p < 4; ++p)
-      av[p] = *reinterpret_cast<const bf16x8 *>(la + (wm * 128 + p * 32 + r) * kLdsRow + ks * 32 + half * 16);
-#pragma unroll
-    for (int q = 0; q < 2; ++q)
-      bv[q] = *reinterpret_cast<const bf16x8 *>(lb + (wn * 64 + q * 32 + r) * kLdsRow + ks * 32 + half * 16);
-#pragma unroll
-    for (int p = 0; p < 4; ++p)
-#pragma unroll
-      for (int q = 0; q < 2; ++q) acc[p][q] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[p], bv[q], acc[p][q], 0, 0, 0);
-  }
-}
-
-// acc += A[m0.., :] B[n0.., :]^T over all of K.  Stage s computes from LDS buffer
-// s % 2 while the loads of stage s + 1 are in flight; they are written to the other
-// buffer, which every wave finished reading before the previous barrier.
-__device__ inline void gemm_nt_bf16(const uint16_t *__restrict__ A, const uint16_t *__restrict__ B, int32_t n1,
-                                    int32_t n2, int32_t K, int m0, int n0, uint8_t *lds, floatx16 (&acc)[4][2]) {
-  constexpr int KE = kChunkBytes / 2;
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int wm = wv >> 1, wn = wv & 1;
-  const bool vec = (static_cast<int64_t>(K) * 2) % 16 == 0 && (reinterpret_cast<uintptr_t>(A) & 15) == 0 &&
-                   (reinterpret_cast<uintptr_t>(B) & 15) == 0;
-  uint8_t *la[2] = {lds, lds + kStageA2 + kStageB2};
-  uint8_t *lb[2] = {lds + kStageA2, lds + 2 * kStageA2 + kStageB2};
-  uint4 ra[kTileM2 / 32], rb[kTileN2 / 32];
-  const int nst = (K + KE - 1) / KE;
-  load_panel<kTileM2>(A, n1, K, m0, 0, vec, ra);
-  load_panel<kTileN2>(B, n2, K, n0, 0, vec, rb);
-  store_panel<kTileM2>(ra, la[0]);
-  store_panel<kTileN2>(rb, lb[0]);
-  __syncthreads();
-  for (int st = 0; st < nst; ++st) {
-    const int cur = st & 1;
-    const bool more = st + 1 < nst;
-    if (more) {
-      load_panel<kTileM2>(A, n1, K, m0, (st + 1) * KE, vec, ra);
-      load_panel<kTileN2>(B, n2, K, n0, (st + 1) * KE, vec, rb);
-    }
-    mma_stage_bf16(la[cur], lb[cur], wm, wn, lane, acc);
-    if (more) {
-      store_panel<kTileM2>(ra, la[cur ^ 1]);
-      store_panel<kTileN2>(rb, lb[cur ^ 1]);
-    }
-    __syncthreads();
-  }
-}
-
-__global__ __launch_bounds__(256, 1) void k_featsim_bf16(const uint16_t *__restrict__ X1, const uint16_t *__restrict__ X2,
-                                                         int32_t d, const uint16_t *__restrict__ R1,
-                                                         const uint16_t *__restrict__ R2, int32_t nL, int32_t n1,
-                                                         int32_t n2, float alpha, float *__restrict__ C) {
-  __shared__ __align__(16) uint8_t lds[2 * (kStageA2 + kStageB2)];
-  const int ntm = (n1 + kTileM2 - 1) / kTileM2, ntn = (n2 + kTileN2 - 1) / kTileN2;
-  const int nb = ntm * ntn;
-  // XCD-aware id (consecutive ids land on different XCDs: give each XCD a
-  // contiguous range of the grouped order), then groups of 8 tile-rows sharing B panels
-  int bid = blockIdx.x;
-  const int full = (nb / 8) * 8;
-  if (bid < full) bid = (bid % 8) * (full / 8) + bid / 8;
-  constexpr int GM = 8;
-  const int group = bid / (GM * ntn);
-  const int first_m = group * GM;
-  const int gsz = min(ntm - first_m, GM);
-  const int tm = first_m + (bid % (GM * ntn)) % gsz;
-  const int tn = (bid % (GM * ntn)) / gsz;
-  const int m0 = tm * kTileM2, n0 = tn * kTileN2;
-  floatx16 accR[4][2], accX[4][2];
-#pragma unroll
-  for (int p = 0; p < 4; ++p)
-#pragma unroll
-    for (int q = 0; q < 2; ++q)
-#pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        accR[p][q][r] = 0.f;
-        accX[p][q][r] = 0.f;
-      }
-  if (nL > 0) gemm_nt_bf16(R1, R2, n1, n2, nL, m0, n0, lds, accR);
-  if (d > 0) gemm_nt_bf16(X1, X2, n1, n2, d, m0, n0, lds, accX);
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int wm = wv >> 1, wn = wv & 1;
-  const float beta = 1.0f - alpha;
-  // accumulator layout of a 32 x 32 block: lane l holds column l % 32 and rows
-  // 8 (r / 4) + 4 (l / 32) + r % 4 for r = 0..15; lanes 0-31 store 128 contiguous bytes
-#pragma unroll
-  for (int p = 0; p < 4; ++p)
-#pragma unroll
-    for (int q = 0; q < 2; ++q) {
-      const int col = n0 + wn * 64 + q * 32 + (lane & 31);
-#pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        const int row = m0 + wm * 128 + p * 32 + (r >> 2) * 8 + (lane >> 5) * 4 + (r & 3);
-        if (row < n1 && col < n2)
-          __builtin_nontemporal_store(alpha * expf(-accR[p][q][r]) + beta * expf(-accX[p][q][r]),
-                                      C + static_cast<int64_t>(row) * n2 + col);
-      }
-    }
-}
-
 int launch_feature_sim(const void *X1, const void *X2, int32_t n1, int32_t n2, int32_t d, int32_t xdt,
                        const void *R1, const void *R2, int32_t nL, int32_t rdt, double alpha, float *C,
                        hipStream_t s) {
@@ -356,9 +201,9 @@ int launch_feature_sim(const void *X1, const void *X2, int32_t n1, int32_t n2, i
   const int nb = ceil_div(n1, kTile) * ceil_div(n2, kTile);
   const float al = static_cast<float>(alpha);
   if (xdt == FA_BF16 && rdt == FA_BF16)
-    FA_LAUNCH(k_featsim_bf16, dim3(ceil_div(n1, kTileM2) * ceil_div(n2, kTileN2)), dim3(256), 0, s,
-              static_cast<const uint16_t *>(X1), static_cast<const uint16_t *>(X2), d,
-              static_cast<const uint16_t *>(R1), static_cast<const uint16_t *>(R2), nL, n1, n2, al, C);
+    FA_LAUNCH((k_featsim<uint16_t, uint16_t>), dim3(nb), dim3(256), 0, s, static_cast<const uint16_t *>(X1),
+              static_cast<const uint16_t *>(X2), d, static_cast<const uint16_t *>(R1),
+              static_cast<const uint16_t *>(R2), nL, n1, n2, al, C);
   else if (xdt == FA_BF16)
     FA_LAUNCH((k_featsim<uint16_t, float>), dim3(nb), dim3(256), 0, s, static_cast<const uint16_t *>(X1),
               static_cast<const uint16_t *>(X2), d, static_cast<const float *>(R1), static_cast<const float *>(R2),

@@ -38,11 +38,15 @@ def make_case(n1, keep_n2, seed, kind="er", deg=8.0, d=24, frac=0.05):
     return make_pair(cfg)
 
 
-@pytest.fixture(scope="module", params=[(600, 2500 // 1, 11), (700, None, 12)], ids=["600x2500", "700x700"])
+@pytest.fixture(scope="module", params=[(600, 2500 // 1, 11, "er"), (700, None, 12, "er"),
+                                        (900, None, 13, "chung_lu")],
+                ids=["600x2500", "700x700", "cl900-hubs"])
 def case(request, api):
-    n1, keep, seed = request.param
+    n1, keep, seed, kind = request.param
     if keep is None:
-        pr = make_case(n1, None, seed)
+        # the Chung-Lu pair has hubs of degree > 64: neighbour lists span several
+        # 64-entry chunks in both SpMM stages
+        pr = make_case(n1, None, seed, kind=kind, deg=12.0 if kind == "chung_lu" else 8.0)
     else:
         # n1 x n2 with n2 > n1: build on the larger side and swap roles
         big = make_case(keep, None, seed)
@@ -61,6 +65,8 @@ def case(request, api):
                        anchors=anc.astype(np.int32), truth=truth)
     rp1, ci1 = O.build_csr(pr.n1, pr.edges1)
     rp2, ci2 = O.build_csr(pr.n2, pr.edges2)
+    if kind == "chung_lu":
+        assert np.diff(rp1).max() > 64 and np.diff(rp2).max() > 64
     inp = api.AlignInputs.from_pair(pr)
     return dict(pr=pr, rp1=rp1, ci1=ci1, rp2=rp2, ci2=ci2, inp=inp)
 
@@ -142,9 +148,9 @@ def test_feature_sim_fp32(api, shape):
 @pytest.mark.parametrize("shape", [(300, 260, 64, 45), (257, 300, 136, 72), (130, 129, 7, 200),
                                    (600, 520, 128, 120), (513, 129, 0, 40), (256, 128, 24, 0)])
 def test_feature_sim_bf16(api, shape):
-    """256 x 128 tiles with ragged edges in both dimensions, several tiles each way;
-    K across several 64-element steps (one to four double-buffered stages), vector
-    (K*2 a multiple of 16) and element staging; either product absent."""
+    """128 x 128 tiles with ragged edges in both dimensions, several tiles each way;
+    K across several 64-element steps, vector (K*2 a multiple of 16) and element
+    staging; either product absent."""
     n1, n2, d, nL = shape
     r = np.random.default_rng(5)
     X1, X2 = r.standard_normal((n1, d)), r.standard_normal((n2, d))
