@@ -177,7 +177,7 @@ def kernel_table(st, pair, nnz1, nnz2, p, binding):
 KERNEL_NAMES = {"lse_col_t": "fa::k_lse_col_t<4, 8>", "lse_row": "fa::k_lse_row<4, 8>",
                 "cost_stage1": "fa::k_stage1<unsigned short, true, 2, 8, true>",
                 "cost_stage2": "fa::k_stage2<true, true>", "plan": "fa::k_plan<4, unsigned short>",
-                "featsim": "fa::k_featsim_bf16"}
+                "featsim": "fa::k_featsim<unsigned short, unsigned short>"}
 
 
 def _counter_rows(d):
@@ -191,11 +191,13 @@ def _counter_rows(d):
     for f in files:
         with open(f, newline="") as fh:
             for r in csv.DictReader(fh):
-                key = (f, r.get("Dispatch_Id") or r.get("Correlation_Id"))
+                key = (f, int(r.get("Dispatch_Id") or r.get("Correlation_Id")))
                 name = r["Kernel_Name"]
+                if name.startswith("void "):
+                    name = name[5:]
                 ent = per.setdefault(key, [name, int(r.get("Grid_Size", 0) or 0), 0.0])
                 ent[2] += float(r["Counter_Value"])
-    return list(per.values())
+    return [per[k] for k in sorted(per)]   # dispatch order
 
 
 def ingest_counters(fetch_dir, write_dir, workload="cl120k:120000x120000"):
@@ -206,10 +208,12 @@ def ingest_counters(fetch_dir, write_dir, workload="cl120k:120000x120000"):
     copy_bytes = 4.0 * 2**30
 
     def calib(rows):
-        vals = [v for name, _, v in rows if "copyBuffer" in name or "copy" in name.lower()]
+        # the calibration copy is the program's first large device copy (--calibrate-copy
+        # runs it before anything else)
+        vals = [v for name, _, v in rows if "copyBuffer" in name and v * 1024.0 > 1e8]
         if not vals:
             raise SystemExit("no copy kernel in the counter record (run with --calibrate-copy)")
-        return copy_bytes / (max(vals) * 1024.0)
+        return copy_bytes / (vals[0] * 1024.0)
 
     ff, wf = calib(fetch), calib(write)
 
