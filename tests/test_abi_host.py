@@ -141,3 +141,23 @@ def test_plain_c_consumer_links_and_runs_host_entry_points(lib, tmp_path):
     e = np.array([[0, 1], [1, 2], [2, 0], [3, 2], [1, 1], [1, 0]])
     rp, ci = O.build_csr(4, e)
     assert vals[0] == rp[-1] and vals[1:6] == list(rp) and vals[6:] == list(ci)
+
+
+def test_stepwise_and_noalloc_host_checks(lib):
+    """Defaults of the new parameters, the static-scratch size query, and argument
+    errors of the stepwise entry points, all decided on the host (no GPU)."""
+    import ctypes as C
+    from paper_2607_11952_amd import api, binding
+    p = api.params()
+    assert p.dual_start == binding.FA_START_ZERO and p.warm_fallback == 1 and p.warm_probe == 0
+    need = lib.raw("fa_sinkhorn_noalloc_need")
+    assert 0 < need(120000, 120000, 1) <= binding.FA_SINKHORN_NOALLOC_SCRATCH
+    assert need(64, 3_000_000, 1) > binding.FA_SINKHORN_NOALLOC_SCRATCH
+    assert need(120000, 120000, 0) > need(120000, 120000, 1)      # column partials without C^T
+    assert need(0, 10, 1) == 0
+    st = binding.fa_stats()
+    # null graphs: refused before any device work
+    assert lib.raw("fa_align_step")(None, None, 0, 0, C.byref(p), None, 0, None, None, None, None, None, None,
+                                    C.byref(st), None, 0, None) == binding.FA_ERR_ARG
+    assert lib.raw("fa_align_end")(None, None, 0, 0, C.byref(p), 0, None, None, None, None, None, None, 0, None,
+                                   None, C.byref(st), None, 0, None) == binding.FA_ERR_ARG
