@@ -373,7 +373,8 @@ static int align_step(AlignCtx &x, int32_t t, const float *mlp, void *S_out, dou
     // rerun from zero duals and the run keeps whichever solve ends closer to the
     // marginals.
     AlignRec r{0, -1, -1, 0, NAN, NAN};
-    int32_t nonfinite = 0;
+    int32_t nonfinite = 0, both = 0;  // host sources of the copies below: alive until the sync
+    double keep_err = 0.0;
     FA_TRY(read_dev(&nonfinite, B.bad + 2, s));
     FA_TRY(read_dev(&r.warm_iters, it_slot, s));
     FA_TRY(read_dev(&r.warm_err, er_slot, s));
@@ -387,7 +388,7 @@ static int align_step(AlignCtx &x, int32_t t, const float *mlp, void *S_out, dou
                           B.sink, s, tm));
       FA_TRY(read_dev(&r.cold_iters, it_slot, s));
       FA_TRY(read_dev(&r.cold_err, er_slot, s));
-      double keep_err = r.cold_err;
+      keep_err = r.cold_err;
       if (r.warm_err <= r.cold_err) {  // the learned start's solve is at least as close: keep it
         FA_HIP(hipMemcpyAsync(a, B.a_keep, sizeof(double) * n2, hipMemcpyDeviceToDevice, s));
         FA_HIP(hipMemcpyAsync(b, B.b_keep, sizeof(double) * n1, hipMemcpyDeviceToDevice, s));
@@ -395,7 +396,7 @@ static int align_step(AlignCtx &x, int32_t t, const float *mlp, void *S_out, dou
       } else {
         r.fell_back = 2;
       }
-      const int32_t both = r.warm_iters + r.cold_iters;  // both solves ran
+      both = r.warm_iters + r.cold_iters;  // both solves ran
       FA_HIP(hipMemcpyAsync(it_slot, &both, sizeof both, hipMemcpyHostToDevice, s));
       FA_HIP(hipMemcpyAsync(er_slot, &keep_err, sizeof keep_err, hipMemcpyHostToDevice, s));
     }

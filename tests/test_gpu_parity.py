@@ -456,22 +456,30 @@ def test_align_small_config_later_solve_starts(api, start):
 
 
 @pytest.mark.parametrize("chunk", [0, 64])
-def test_align_unequal_sizes_ragged(api, chunk):
+def test_align_unequal_sizes_ragged(api, chunk, monkeypatch):
     """n1 > n2, odd n2 (scalar paths), isolated nodes, chunked cost rebuild.
 
-    This pair is ill-conditioned: in the FP64 oracle, a relative perturbation of
-    1e-7 in log(Abar1^T S Abar2) moves the final plan by 7.5e-5 (max-abs/max), and
-    rounding the stored cost to FP32 moves it by 6e-4 (measured once with the
-    oracle).  The FP32 path is therefore held to 5e-3 here and to the 1e-4 bar on
-    the well-conditioned small workload; the argmax must still agree."""
+    This pair is ill-conditioned: in the FP64 oracle a relative perturbation of
+    1e-7 in log(Abar1^T S Abar2) already moves the final plan by 7.5e-5
+    (max-abs/max).  The bar is measured rather than fixed: four times the effect of
+    storing the cost in FP32, i.e. the oracle rerun with its cost rounded to FP32
+    after every rebuild (as the library stores it), and at least the 1e-4 of the
+    well-conditioned small workload; the argmax must still agree."""
     cfg = PairConfig("r", 420, "chung_lu", 10.0, noise=0.1, keep_n2=333, d=16, sigma=0.2, anchor_frac=0.08,
                      seed=21)
     pr = make_pair(cfg)
     p = O.Params(eps=0.05, outer_iters=4, inner_iters=30)
     ref, res = _align_both(api, pr, p, chunk_rows=chunk)
+    exact = O.cost_update
+    monkeypatch.setattr(O, "cost_update", lambda *a, **k: exact(*a, **k).astype(np.float32).astype(np.float64))
+    rp1, ci1 = O.build_csr(pr.n1, pr.edges1)
+    rp2, ci2 = O.build_csr(pr.n2, pr.edges2)
+    f32 = O.align(pr.n1, rp1, ci1, pr.n2, rp2, ci2, pr.X1, pr.X2, pr.anchors, p)
+    monkeypatch.setattr(O, "cost_update", exact)
+    bar = max(1e-4, 4.0 * _plan_err(f32["S"], ref["S"]))
     e = _plan_err(_np(res.S), ref["S"])
     agree = (_np(res.argmax) == ref["argmax"]).mean()
-    assert e <= 5e-3 and agree >= 0.99, (e, agree)
+    assert e <= bar and agree >= 0.99, (e, bar, agree)
 
 
 @pytest.mark.parametrize("form", ["f32", "bf16"])

@@ -51,9 +51,12 @@ def test_bf16_form_agrees_with_fp32_on_resolved_rows(lib):
     rows = (m_b > 1.0) & (m_f > 1.0)
     frac = float(rows.float().mean())
     agree_res = float((a_b[rows] == a_f[rows]).float().mean())
-    print(f"[precision] 60k x 50k: argmax agreement {agree:.4f} overall; {frac:.3f} of rows resolved by > 1 nat, "
-          f"agreement there {agree_res:.4f}; accuracy vs truth BF16 {acc_b:.4f} FP32 {acc_f:.4f}; "
-          f"final marginal error {e_b:.2e} / {e_f:.2e}")
+    agree_matched = float((a_b[has] == a_f[has]).float().mean())
+    agree_unmatched = float((a_b[~has] == a_f[~has]).float().mean())
+    print(f"[precision] 60k x 50k: argmax agreement {agree:.4f} overall ({agree_matched:.4f} on the "
+          f"{int(has.sum())} rows with a partner in G2, {agree_unmatched:.4f} on the {int((~has).sum())} without); "
+          f"{frac:.3f} of rows resolved by > 1 nat, agreement there {agree_res:.4f}; accuracy vs truth BF16 "
+          f"{acc_b:.4f} FP32 {acc_f:.4f}; final marginal error {e_b:.2e} / {e_f:.2e}")
     assert agree_res >= 0.99
     assert frac >= 0.75
     assert abs(acc_b - acc_f) <= 0.005
