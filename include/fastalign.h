@@ -355,7 +355,10 @@ int fa_align(const fa_csr *A1, const fa_csr *A2, const float *X1, const float *X
  *   acc (host, nullable): phase_ms[0] accumulates the call's device time and, with
  *   p->profile, kernel_ms / kernel_calls its launches (the similarity GEMM).
  * fa_align_step: outer iteration t (cost rebuild, inner solve from the start the
- *   params select, plan).  argmax_out/truth/rank_out (nullable; truth and rank_out
+ *   params select, plan).  Steps run in order, t = 0, 1, 2, ..., after
+ *   fa_align_begin: each reads the state the previous ones left in the workspace
+ *   (the plan, the duals, the sums behind FA_START_MEAN); calls out of order are
+ *   not detected and give another (still finite-size, in-bounds) computation.  argmax_out/truth/rank_out (nullable; truth and rank_out
  *   together) are written from this step's plan, as fa_align does on its last step.
  *   Synchronises at the end; returns FA_ERR_NUMERIC if the solve's marginal error
  *   is not finite.  acc (host, nullable): with p->profile its phase_ms,
