@@ -60,6 +60,7 @@ def parse():
     ap.add_argument("--no-plain", action="store_true", help="skip the plain FP32 comparison run")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cold", action="store_true", help="headline form without the learned warm start")
+    ap.add_argument("--weights", default="", help="warm-start network (default: the package's trained network)")
     ap.add_argument("--start", default="mean", choices=["zero", "carry", "mean"],
                     help="headline form: start of the inner solves after the first")
     ap.add_argument("--warm-probe", type=int, default=50,
@@ -291,7 +292,8 @@ def main():
     inp = api.AlignInputs.from_pair(pair, dev)
     torch.cuda.synchronize()
 
-    mlp = None if args.cold else warm.load_weights(dev)
+    wpath = args.weights or warm.WEIGHTS
+    mlp = None if args.cold else warm.load_weights(dev, wpath)
     common = dict(eps=cfg.eps, outer_iters=T, inner_iters=cfg.inner_iters, tol=1e-6, check_every=1, profile=1,
                   plan_in_ct=args.plan_in_ct)
     # top-2 lists of the final plan give each row's margin log(S_top / S_second)
@@ -456,7 +458,8 @@ def main():
                             n1=pair.n1, n2=pair.n2, outer_iters=T, inner_cap=cfg.inner_iters, tol=1e-6,
                             step="one outer iteration (cost rebuild + inner solve + plan) of the headline form",
                             value="device time of the whole headline alignment (Phase 1 + all outer iterations)"),
-                warm_start=mlp is not None, warm_probe=args.warm_probe, dual_start=args.start,
+                warm_start=mlp is not None, warm_weights=os.path.relpath(wpath, ROOT) if mlp is not None else None,
+                warm_probe=args.warm_probe, dual_start=args.start,
                 plan_in_ct=args.plan_in_ct, headline=head,
                 plain_fp32=plain, fp32_same_start=f32s, argmax_agreement=agree,
                 speedup_vs_plain=(plain["align_s"] / head["align_s"] if plain else None),

@@ -17,7 +17,12 @@ from zero - marginal error after K iterations, the iterations the learned start
 needs to reach the cold solve's final error, and the iterations both need to
 reach a fixed tolerance (with the argmax agreement of the two plans there).
 
+Two families: "mixed" (the above; the shipped weights/warm_mlp.bin) and "cl",
+the benchmark recipe at n = 20,000-40,000 (Chung-Lu, degree 20, d = 128, 2%
+anchors; training seeds from 7000, never the benchmark pair's).
+
 Usage: python -m paper_2607_11952_amd.train_warm --pairs 2000 --out <weights>
+       python -m paper_2607_11952_amd.train_warm --family cl --pairs 200 --out <weights>
        python -m paper_2607_11952_amd.train_warm --eval-only --weights <weights>
 """
 from __future__ import annotations
@@ -47,6 +52,18 @@ def family(seed: int, n: int = 0):
         eps=EPS)
 
 
+def family_cl(seed: int, n: int = 0):
+    """The benchmark recipe's family at smaller sizes: Chung-Lu, exponent 2.5, average
+    degree 20, 10% edge noise, 128-dim attributes with sigma 0.2, 2% anchors, eps 0.02;
+    n ~ U{20000..40000} (seeds of their own, never the benchmark pair's)."""
+    r = np.random.default_rng(seed)
+    return dataclasses.replace(CONFIGS["cl120k"], name="cl_family", n1=n or int(r.integers(20000, 40001)),
+                               seed=seed)
+
+
+FAMILIES = {"mixed": (family, 1000), "cl": (family_cl, 7000)}   # generator, first training seed
+
+
 def first_solve(inp, inner: int, mlp=None, tol: float = 0.0, fallback: bool = False, probe: int = 0):
     """One outer iteration (the first inner solve); with a network, the learned start
     alone (fallback False) or with the library's cold rerun when it misses tol within
@@ -56,8 +73,8 @@ def first_solve(inp, inner: int, mlp=None, tol: float = 0.0, fallback: bool = Fa
     return api.align(inp, p, mlp=mlp)
 
 
-def pair_data(seed: int, inner: int, device):
-    pr = make_pair(family(seed))
+def pair_data(seed: int, inner: int, device, fam=family):
+    pr = make_pair(fam(seed))
     inp = api.AlignInputs.from_pair(pr, device)
     res = first_solve(inp, inner)
     b = res.b.clone()
@@ -109,10 +126,10 @@ def train(F: torch.Tensor, t: torch.Tensor, epochs: int, batch: int, lr: float, 
 
 
 def evaluate(prm: torch.Tensor, seeds, n: int, K: int, device, log=print, tol: float = 1e-6, cap: int = 1000,
-             probe: int = 0):
+             probe: int = 0, fam=family):
     rows = []
     for s in seeds:
-        pr = make_pair(family(s, n))
+        pr = make_pair(fam(s, n))
         inp = api.AlignInputs.from_pair(pr, device)
         cold = first_solve(inp, K)
         warm_ = first_solve(inp, K, mlp=prm)
@@ -216,6 +233,9 @@ def main():
     ap.add_argument("--probe", type=int, default=50,
                     help="iterations granted to the learned start before the cold rerun (0: the cap)")
     ap.add_argument("--out", default=warm.WEIGHTS)
+    ap.add_argument("--family", default="mixed", choices=sorted(FAMILIES),
+                    help="mixed: the Erdos-Renyi / Chung-Lu family of n = 2,000-8,000; cl: the benchmark recipe "
+                         "(Chung-Lu, degree 20, d = 128, 2% anchors) at n = 20,000-40,000")
     ap.add_argument("--report", default="")
     ap.add_argument("--md", default="", help="markdown record of the evaluation")
     ap.add_argument("--merge", nargs="*", default=None,
@@ -242,10 +262,11 @@ def main():
     log = lambda m: print(m, file=sys.stderr, flush=True)
     t0 = time.time()
     seeds = range(args.eval_seed0, args.eval_seed0 + args.eval_pairs)
+    fam, seed0 = FAMILIES[args.family]
     if args.eval_only:
         prm = torch.from_numpy(warm.read_weights(args.weights)).to(dev)
         rows = evaluate(prm, seeds, args.eval_n, args.eval_k, dev, log=log, tol=args.tol, cap=args.cap,
-                        probe=args.probe)
+                        probe=args.probe, fam=fam)
         summ = summarize(rows)
         if args.report:
             with open(args.report, "w") as f:
@@ -254,7 +275,7 @@ def main():
         return
     Fs, ts, errs = [], [], []
     for k in range(args.pairs):
-        F, t, e = pair_data(1000 + k, args.inner, dev)
+        F, t, e = pair_data(seed0 + k, args.inner, dev, fam)
         Fs.append(F)
         ts.append(t)
         errs.append(e)
@@ -268,7 +289,7 @@ def main():
     warm.save_weights(prm.cpu().numpy(), args.out)
     log(f"[train] saved {args.out}")
     rows = evaluate(prm, seeds, args.eval_n, args.eval_k, dev, log=log, tol=args.tol, cap=args.cap,
-                    probe=args.probe)
+                    probe=args.probe, fam=fam)
     summ = summarize(rows)
     rep = dict(pairs=args.pairs, nodes=int(F.shape[0]), target_var=float(t.var()), mse_per_epoch=hist,
                eval=rows, summary=summ, seconds=time.time() - t0)
