@@ -40,7 +40,7 @@ sys.path.insert(0, ROOT)
 METRIC = "align time (s) + SpMM HBM GB/s at n=120k: plain FP32 vs BF16+warm start @1e-6"
 HBM_PEAK_GBS = 8000.0
 KERNELS = ["lse_col_partial", "lse_col_merge", "lse_row", "cost_stage1", "cost_stage2", "plan", "featsim", "lse_col_t",
-           "transpose", "topk"]
+           "transpose", "topk", "sink_fused"]
 MFMA_PEAK_TFLOPS = {"bf16": 2500.0, "f32": 157.3}   # dense matrix-core peaks of the part
 T_START = time.time()
 
@@ -89,7 +89,7 @@ TRAFFIC = os.path.join(ROOT, "profiles", "traffic.json")
 KERNEL_SOURCES = {"lse_col_partial": "fa_sinkhorn.hip", "lse_col_merge": "fa_sinkhorn.hip", "lse_row": "fa_sinkhorn.hip",
                   "lse_col_t": "fa_sinkhorn.hip", "featsim": "fa_gemm.hip",
                   "plan": "fa_sinkhorn.hip", "cost_stage1": "fa_spmm.hip", "cost_stage2": "fa_spmm.hip",
-                  "transpose": "fa_topk.hip", "topk": "fa_topk.hip"}
+                  "transpose": "fa_topk.hip", "topk": "fa_topk.hip", "sink_fused": "fa_sinkhorn.hip"}
 
 
 def source_digest(kernel=None):
@@ -123,7 +123,7 @@ def measured_traffic(kernel, workload):
 def algorithmic_bytes(kind, n1, n2, nnz1, nnz2, chunk, sbytes, zpair, transposed=True):
     """Compulsory HBM bytes per launch of each kernel class (see the design notes)."""
     N = n1 * n2
-    if kind in ("lse_col_partial", "lse_row", "lse_col_t"):
+    if kind in ("lse_col_partial", "lse_row", "lse_col_t", "sink_fused"):
         return 4 * N + 8 * (n1 + n2)                 # one FP32 pass over C (or C^T) + both dual vectors
     if kind == "lse_col_merge":
         return 8 * n2 * 3
@@ -175,7 +175,8 @@ def kernel_table(st, pair, nnz1, nnz2, p, binding):
 
 
 # kernel class of the headline form -> the kernel's name prefix in a rocprofv3 record
-KERNEL_NAMES = {"lse_col_t": "fa::k_lse_col_t<4, 8>", "lse_row": "fa::k_lse_row<4, 8>",
+KERNEL_NAMES = {"sink_fused": "fa::k_sink_fused<4, 2>", "lse_col_t": "fa::k_lse_col_t<4, 8>",
+                "lse_col_partial": "fa::k_lse_col_partial<4, 4>", "lse_row": "fa::k_lse_row<4, 8>",
                 "cost_stage1": "fa::k_stage1<unsigned short, true, 2, 8, true>",
                 "cost_stage2": "fa::k_stage2<true, true>", "plan": "fa::k_plan<4, unsigned short>",
                 "featsim": "fa::k_featsim<unsigned short, unsigned short>"}

@@ -43,7 +43,9 @@ typedef enum {
   FA_ERR_WORKSPACE = -4,     /* workspace missing or smaller than required */
   FA_ERR_NUMERIC = -6,       /* non-finite value where a finite one is required */
   FA_ERR_HIP = -7,           /* a HIP runtime call failed */
-  FA_ERR_DEVICE = -8         /* the current device is not a gfx950 GPU */
+  FA_ERR_DEVICE = -8,        /* the current device is not a gfx950 GPU */
+  FA_ERR_SYNC = -9           /* a bounded wait between co-resident workgroups of the
+                                single-pass Sinkhorn iteration gave up (outputs undefined) */
 } fa_status;
 
 typedef enum { FA_F32 = 0, FA_BF16 = 1, FA_F64 = 2 } fa_dtype;
@@ -107,6 +109,10 @@ typedef struct {
                          A learned start either
                          converges within a few dozen iterations or decays at the cold rate,
                          so a short probe bounds what a miss costs. */
+  int32_t sink_fused; /* 1: inner solves use the single-pass iteration of fa_sinkhorn_fused
+                         (one read of C per iteration instead of two; C^T is then needed
+                         only by plan_in_ct) when the shape and the device allow it, and
+                         the two-pass iteration otherwise; 0: always two passes */
 } fa_params;
 
 /* Starts of the inner solves after the first (fa_params.dual_start). */
@@ -132,9 +138,10 @@ typedef struct {
    * [0] column LSE partials, [1] column merge, [2] row LSE, [3] cost stage 1
    * (left SpMM), [4] cost stage 2 (right SpMM + fused assembly), [5] plan,
    * [6] node similarity (MFMA GEMM), [7] column pass over C^T, [8] transpose of C
-   * (plan_in_ct), [9] top-k plan */
-  double kernel_ms[10];
-  int32_t kernel_calls[10];
+   * (plan_in_ct), [9] top-k plan, [10] single-pass iteration (its merge counts
+   * under [1]) */
+  double kernel_ms[11];
+  int32_t kernel_calls[11];
 } fa_stats;
 
 /* Thread-local message describing the last non-OK status. */
@@ -144,7 +151,8 @@ const char *fa_last_error(void);
  * lambda_e = lambda_n = lambda_a = 1, lambda_p = eps_anchor = eps,
  * delta_nbr 1e-30, tol 0, k_r 10, k_node 1, 10 outer x 50 inner iterations,
  * check_every 1, FP32 plan and features, feat_l2norm 1, cold start, zero starts
- * for later solves, transpose_cost 1, warm_fallback 1. */
+ * for later solves, transpose_cost 0, plan_in_ct 0, warm_fallback 1, warm_probe 0,
+ * sink_fused 1. */
 void fa_default_params(fa_params *p);
 
 /* 0 if the current HIP device is a gfx950 GPU, else FA_ERR_DEVICE. */
@@ -283,6 +291,34 @@ size_t fa_sinkhorn_noalloc_need(int32_t n1, int32_t n2, int32_t transposed);
 int fa_sinkhorn_noalloc(const float *C, const float *Ct, int32_t n1, int32_t n2, double eps, double *a,
                         double *b, int32_t max_iter, double tol, int32_t check_every, int32_t *dev_iters,
                         double *dev_err, void *stream);
+
+/* Single-pass form of fa_sinkhorn (Eq. (3), the same iteration): C is read once
+ * per iteration instead of twice, and no C^T is needed.  Iterations 0 and 1 run
+ * as in fa_sinkhorn without C^T; from iteration 2 on one pass over C does the
+ * b-update of the iteration and the column sums of the a-update after it.  Each
+ * row is split over gc co-resident workgroups (column slices of up to 4,096
+ * columns held in registers) that exchange their partial row sums before
+ * adding the row's updated plan entries to their column sums; the exponent
+ * (a_j + b_i - C_ij)/eps is formed in FP64 as in fa_sinkhorn and needs no running
+ * maximum (after an a-update no plan entry exceeds nu_j, and after a b-update
+ * no row sum of the next plan falls below mu_i * min_j nu_j).  Results equal
+ * fa_sinkhorn's up to summation order (same iteration count when both stop on
+ * the same check).  Arguments as fa_sinkhorn minus Ct; ws >=
+ * fa_sinkhorn_fused_workspace_size(n1, n2) bytes.  Needs n2 % 4 == 0 and a device
+ * that co-schedules the grid (fa_sinkhorn_fused_grid); otherwise every iteration
+ * takes the two-pass form.  The partners' waits are bounded (fa_set_sync_spin_limit):
+ * a wait that gives up stops the solve, dev_iters becomes -1 and dev_err NaN, and
+ * with host_iters/host_err the call returns FA_ERR_SYNC. */
+size_t fa_sinkhorn_fused_workspace_size(int32_t n1, int32_t n2);
+int fa_sinkhorn_fused(const float *C, int32_t n1, int32_t n2, double eps, double *a, double *b, int32_t max_iter,
+                      double tol, int32_t check_every, int32_t *dev_iters, double *dev_err, int32_t *host_iters,
+                      double *host_err, void *ws, size_t ws_bytes, void *stream);
+/* The single-pass grid on the current device: *gr row groups x *gc partners per
+ * row (host outputs).  FA_ERR_SHAPE if the single pass is not available there. */
+int fa_sinkhorn_fused_grid(int32_t n1, int32_t n2, int32_t *gr, int32_t *gc);
+/* Bound on the polls of one partner wait of the single pass (>= 1; default
+ * 4,194,304, about four seconds).  Process-wide; returns the previous bound. */
+int32_t fa_set_sync_spin_limit(int32_t polls);
 
 /* Plan recovery S_ij = exp((a_j + b_i - C_ij)/eps) (Eq. (4)) stored as s_dtype
  * (FA_F32 or FA_BF16, round-to-nearest-even).  If argmax is non-NULL it also

@@ -91,9 +91,11 @@ def params(**kw) -> B.fa_params:
         if k == "dual_start" and isinstance(v, str):
             v = {"zero": B.FA_START_ZERO, "carry": B.FA_START_CARRY, "mean": B.FA_START_MEAN}[v]
         if k in ("feat_l2norm", "warm_start", "profile", "dual_start", "transpose_cost", "plan_in_ct",
-                 "warm_fallback", "warm_probe"):
+                 "warm_fallback", "warm_probe", "sink_fused"):
             v = int(v)
         setattr(p, k, v)
+    if p.plan_in_ct and "transpose_cost" not in kw:
+        p.transpose_cost = 1  # the working plan lives in the C^T buffer
     if "lambda_p" not in kw:
         p.lambda_p = p.eps
     if "eps_anchor" not in kw:
@@ -185,6 +187,28 @@ def sinkhorn(Cm: torch.Tensor, eps: float, a: torch.Tensor, b: torch.Tensor, max
     _lib().call("fa_sinkhorn", _ptr(Cm), _ptr(Ct), n1, n2, float(eps), _ptr(a), _ptr(b), int(max_iter), float(tol),
                 int(check_every), _ptr(di), _ptr(de), C.byref(hi), C.byref(he), _ptr(ws), nb, _stream())
     return hi.value, he.value
+
+
+def sinkhorn_fused(Cm: torch.Tensor, eps: float, a: torch.Tensor, b: torch.Tensor, max_iter: int, tol: float = 0.0,
+                   check_every: int = 1):
+    """The single-pass iteration (one read of C per iteration); in place on a, b.
+    Returns (iterations, marginal error)."""
+    n1, n2 = Cm.shape
+    nb = _lib().raw("fa_sinkhorn_fused_workspace_size")(n1, n2)
+    ws = torch.empty(nb, dtype=torch.uint8, device=Cm.device)
+    di = torch.zeros(1, dtype=torch.int32, device=Cm.device)
+    de = torch.zeros(1, dtype=torch.float64, device=Cm.device)
+    hi, he = C.c_int32(0), C.c_double(0)
+    _lib().call("fa_sinkhorn_fused", _ptr(Cm), n1, n2, float(eps), _ptr(a), _ptr(b), int(max_iter), float(tol),
+                int(check_every), _ptr(di), _ptr(de), C.byref(hi), C.byref(he), _ptr(ws), nb, _stream())
+    return hi.value, he.value
+
+
+def sinkhorn_fused_grid(n1: int, n2: int):
+    """(row groups, partners per row) of the single pass on the current device, or None."""
+    gr, gc = C.c_int32(0), C.c_int32(0)
+    st = _lib().raw("fa_sinkhorn_fused_grid")(int(n1), int(n2), C.byref(gr), C.byref(gc))
+    return (gr.value, gc.value) if st == 0 else None
 
 
 def plan(Cm: torch.Tensor, eps: float, a: torch.Tensor, b: torch.Tensor, dtype=torch.float32, argmax: bool = False,

@@ -14,7 +14,7 @@ LIB_PATH = os.path.join(HERE, "libfastalign.so")
 
 FA_OK, FA_WARN_NOT_CONVERGED = 0, 1
 FA_ERR_ARG, FA_ERR_SHAPE, FA_ERR_CSR, FA_ERR_WORKSPACE = -1, -2, -3, -4
-FA_ERR_NUMERIC, FA_ERR_HIP, FA_ERR_DEVICE = -6, -7, -8
+FA_ERR_NUMERIC, FA_ERR_HIP, FA_ERR_DEVICE, FA_ERR_SYNC = -6, -7, -8, -9
 FA_F32, FA_BF16, FA_F64 = 0, 1, 2
 FA_START_ZERO, FA_START_CARRY, FA_START_MEAN = 0, 1, 2
 FA_SINKHORN_NOALLOC_SCRATCH = 16 << 20
@@ -27,6 +27,7 @@ EXPORTS = [
     "fa_node_features", "fa_mlp_param_count", "fa_mlp_act_floats", "fa_mlp_forward",
     "fa_mlp_backward", "fa_adam_step", "fa_stream_read", "fa_plan_topk",
     "fa_align_begin", "fa_align_step", "fa_align_end", "fa_sinkhorn_noalloc_need", "fa_sinkhorn_noalloc",
+    "fa_sinkhorn_fused_workspace_size", "fa_sinkhorn_fused", "fa_sinkhorn_fused_grid", "fa_set_sync_spin_limit",
 ]
 
 
@@ -48,6 +49,7 @@ class fa_params(C.Structure):
         ("plan_in_ct", C.c_int32),
         ("warm_fallback", C.c_int32),
         ("warm_probe", C.c_int32),
+        ("sink_fused", C.c_int32),
     ]
 
 
@@ -58,7 +60,7 @@ class fa_stats(C.Structure):
         ("warm_iters", C.c_int32), ("cold_iters", C.c_int32), ("warm_err", C.c_double), ("cold_err", C.c_double),
         ("phase_ms", C.c_double * 4),
         ("inner_iters", C.c_int32 * 64), ("inner_err", C.c_double * 64),
-        ("kernel_ms", C.c_double * 10), ("kernel_calls", C.c_int32 * 10),
+        ("kernel_ms", C.c_double * 11), ("kernel_calls", C.c_int32 * 11),
     ]
 
 
@@ -87,6 +89,10 @@ _SIGS = {
     "fa_sinkhorn": (C.c_int, [_P, _P, _I32, _I32, _D, _P, _P, _I32, _D, _I32, _P, _P, _P, _P, _P, _SZ, _P]),
     "fa_sinkhorn_noalloc_need": (_SZ, [_I32, _I32, _I32]),
     "fa_sinkhorn_noalloc": (C.c_int, [_P, _P, _I32, _I32, _D, _P, _P, _I32, _D, _I32, _P, _P, _P]),
+    "fa_sinkhorn_fused_workspace_size": (_SZ, [_I32, _I32]),
+    "fa_sinkhorn_fused": (C.c_int, [_P, _I32, _I32, _D, _P, _P, _I32, _D, _I32, _P, _P, _P, _P, _P, _SZ, _P]),
+    "fa_sinkhorn_fused_grid": (C.c_int, [_I32, _I32, _P, _P]),
+    "fa_set_sync_spin_limit": (_I32, [_I32]),
     "fa_plan": (C.c_int, [_P, _I32, _I32, _D, _P, _P, _P, _I32, _P, _P, _P, _P]),
     "fa_plan_topk": (C.c_int, [_P, _I32, _I32, _D, _P, _P, _I32, _P, _P, _P]),
     "fa_align_workspace_size": (_SZ, [_I32, _I32, _I32, _I32, _I64, _I64, C.POINTER(fa_params)]),

@@ -203,7 +203,7 @@ extern "C" size_t fa_align_workspace_size(int32_t n1, int32_t n2, int32_t d, int
   Sizer z;
   carve_align(z, n1, n2, d, nL, nnz1, nnz2, p, L, nullptr);
   z.take<AlignRec>(1);
-  z.off = align_up(z.off, 256) + sinkhorn_ws_bytes(n1, n2);
+  z.off = align_up(z.off, 256) + sinkhorn_ws_bytes(n1, n2, p->sink_fused != 0);
   return z.off + 256;
 }
 
@@ -225,7 +225,7 @@ static int open_ctx(AlignCtx &x, const fa_csr *A1, const fa_csr *A2, int32_t d, 
   Carver cv(ws, ws_bytes);
   carve_align(cv, x.n1, x.n2, d, nL, A1->nnz, A2->nnz, p, x.L, &x.B);
   x.rec = cv.take<AlignRec>(1);
-  FA_TRY(carve_sinkhorn(cv, x.n1, x.n2, x.B.sink));
+  FA_TRY(carve_sinkhorn(cv, x.n1, x.n2, x.B.sink, p->sink_fused != 0));
   FA_REQUIRE(cv.ok, FA_ERR_WORKSPACE, "fa_align: workspace carve failed");
   return FA_OK;
 }
@@ -308,6 +308,17 @@ static int align_begin(AlignCtx &x, const float *X1, const float *X2, const int3
   return FA_OK;
 }
 
+// FA_ERR_SYNC if the last inner solve gave up a partner wait of the single pass
+// (synchronises; only the single-pass form can give up).
+static int sink_ok(const AlignCtx &x, int32_t t) {
+  if (!x.p->sink_fused) return FA_OK;
+  int32_t fault = 0;
+  FA_TRY(sinkhorn_fault(x.B.sink, x.s, &fault));
+  FA_REQUIRE(!fault, FA_ERR_SYNC, "fa_align: a partner wait of the single-pass Sinkhorn gave up at outer iteration %d",
+             t);
+  return FA_OK;
+}
+
 template <typename T>
 static int read_dev(T *host, const T *dev, hipStream_t s) {
   FA_HIP(hipMemcpyAsync(host, dev, sizeof(T), hipMemcpyDeviceToHost, s));
@@ -368,6 +379,7 @@ static int align_step(AlignCtx &x, int32_t t, const float *mlp, void *S_out, dou
   const bool probe = warm && p->warm_fallback && p->tol > 0 && p->warm_probe > 0 && p->warm_probe < p->inner_iters;
   const int32_t budget = probe ? p->warm_probe : p->inner_iters;
   FA_TRY(run_sinkhorn(B.C, Ct, n1, n2, p->eps, a, b, budget, p->tol, p->check_every, it_slot, er_slot, B.sink, s, tm));
+  FA_TRY(sink_ok(x, t));
   if (warm) {
     // The cold start stays the reference: a learned start whose solve misses tol is
     // rerun from zero duals and the run keeps whichever solve ends closer to the
@@ -386,6 +398,7 @@ static int align_step(AlignCtx &x, int32_t t, const float *mlp, void *S_out, dou
       FA_TRY(launch_fill_f64(b, n1, 0.0, s));
       FA_TRY(run_sinkhorn(B.C, Ct, n1, n2, p->eps, a, b, p->inner_iters, p->tol, p->check_every, it_slot, er_slot,
                           B.sink, s, tm));
+      FA_TRY(sink_ok(x, t));
       FA_TRY(read_dev(&r.cold_iters, it_slot, s));
       FA_TRY(read_dev(&r.cold_err, er_slot, s));
       keep_err = r.cold_err;

@@ -230,6 +230,7 @@ enum KernelKind {
   KK_COL_T,
   KK_TRANSPOSE,
   KK_TOPK,
+  KK_FUSED,
   KK_COUNT
 };
 struct KTimer {

@@ -48,10 +48,11 @@ extern "C" void fa_default_params(fa_params *p) {
   p->chunk_rows = 0;
   p->profile = 0;
   p->dual_start = FA_START_ZERO;
-  p->transpose_cost = 1;
+  p->transpose_cost = 0;
   p->plan_in_ct = 0;
   p->warm_fallback = 1;
   p->warm_probe = 0;
+  p->sink_fused = 1;
 }
 
 extern "C" int fa_device_check(void) {

@@ -55,12 +55,18 @@ struct SinkWs {
   double *ps;     // column partial sums   [nsplit * n2]
   double *a_next; // candidate a            [n2]
   double *errp;   // per-block L1 error partials
-  int32_t *ctl;   // [0] done flag, [1] iterations done, [2] which buffer holds a
+  int32_t *ctl;   // [0] done flag, [1] iterations done, [2] which buffer holds a, [4] abandoned wait
   double *err;    // [1] final marginal error
+  uint64_t *part; // single-pass form (nullptr: two passes per iteration): tagged row partials [n1 * gc]
+  double *pcol;   //   column sums per row group [gr * n2]
   int nsplit, nerrblk;
 };
-size_t sinkhorn_ws_bytes(int32_t n1, int32_t n2);
-int carve_sinkhorn(Carver &cv, int32_t n1, int32_t n2, SinkWs &w);
+// fused: also carve the single-pass exchange (the loop then uses it when the
+// shape and the device allow).
+size_t sinkhorn_ws_bytes(int32_t n1, int32_t n2, bool fused);
+int carve_sinkhorn(Carver &cv, int32_t n1, int32_t n2, SinkWs &w, bool fused);
+// 1 if the last solve on this workspace abandoned a partner wait (reads the device; synchronises s).
+int sinkhorn_fault(const SinkWs &w, hipStream_t s, int32_t *fault);
 // Ct (nullable): C^T, row-major n2 x n1; when given the column pass streams it row by row.
 int run_sinkhorn(const float *C, const float *Ct, int32_t n1, int32_t n2, double eps, double *a, double *b,
                  int32_t max_iter, double tol, int32_t check_every, int32_t *dev_iters, double *dev_err,

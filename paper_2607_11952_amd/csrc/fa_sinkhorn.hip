@@ -21,8 +21,22 @@
 // (b-update) gives each workgroup eight rows and reduces across the workgroup with
 // wavefront shuffles.
 //
+// Single-pass form (fa_sinkhorn_fused, and fa_align with sink_fused): from the
+// third iteration on, one pass over C does the b-update of an iteration and the
+// column sums of the a-update that follows, so C is read once per iteration
+// instead of twice.  A row's b needs the whole row, and the row's plan entries
+// after that update feed every column sum; a row is split across gc partner
+// workgroups (column slices, kept in registers), which exchange their partial row
+// sums through tagged 64-bit slots (a bounded wait on co-resident workgroups,
+// launched cooperatively), then fold the row's new plan entries into
+// per-workgroup column sums.  No running maximum is needed:
+// after an a-update every plan entry is at most nu_j, and once b comes from a
+// b-update every row sum is at least mu_i * min_j nu_j, so 2^y with the exponent
+// y = (a_j + b_i - C_ij) log2(e)/eps of the current duals stays in FP32 range.
+//
 // The loop never waits for the host: a device control word marks convergence and
 // every later kernel of the loop returns at its first instruction.
+#include <atomic>
 #include <mutex>
 
 #include "fa_common.h"
@@ -35,6 +49,7 @@ struct SinkCtl {
   int32_t iters;
   int32_t which;    // buffer (0: caller's a, 1: scratch) that holds the final a
   uint32_t arrive;  // last-block counter of the merge kernel
+  int32_t fault;    // a partner wait of the single-pass form exceeded its bound
 };
 
 constexpr int kColTRowsPerWg = 8;  // columns (rows of C^T) per workgroup of the transposed column pass
@@ -59,38 +74,81 @@ static SinkLayout sink_layout(int32_t n1, int32_t n2) {
   return L;
 }
 
-// The column partials pm/ps serve only the strip-based column pass; a caller that
-// always passes C^T (transposed_only) needs none of them.
-static size_t sink_scratch_bytes(int32_t n1, int32_t n2, bool transposed_only) {
+// Single-pass form: kFuseQ quads (four consecutive columns) per thread and
+// 256 threads per workgroup, so a partner's slice holds up to 4096 columns;
+// kFuseK rows per exchange batch; at most kFuseMaxGrid co-resident workgroups.
+constexpr int kFuseQ = 4;
+constexpr int kFuseK = 2;
+constexpr int kFuseMaxGrid = 2048;
+constexpr int32_t kFuseSpinDefault = 1 << 22;
+
+// Partners per row: the smallest power of two whose slices fit kFuseQ quads per thread.
+static int fuse_partners(int32_t n2) {
+  const int64_t nq = n2 / 4;
+  const int64_t need = (nq + 256 * kFuseQ - 1) / (256 * kFuseQ);
+  int gc = 1;
+  while (gc < need) gc <<= 1;
+  return gc;
+}
+static int fuse_groups_cap(int32_t n2) {
+  const int gc = fuse_partners(n2);
+  return gc >= kFuseMaxGrid ? 1 : kFuseMaxGrid / gc;
+}
+
+// Which scratch a solve carves: the strip partials pm/ps serve the column pass
+// without C^T; SINK_FUSED adds the single-pass exchange (a tagged row partial per
+// row and partner, column sums per row group).
+enum SinkMode { SINK_TWO_PASS = 0, SINK_T_ONLY = 1, SINK_FUSED = 2 };
+
+template <typename Z>
+static void take_sink(Z &z, int32_t n1, int32_t n2, SinkMode mode) {
   SinkLayout L = sink_layout(n1, n2);
-  Sizer z;
-  if (!transposed_only) {
-    z.take<double>(static_cast<size_t>(L.nsplit) * n2);
-    z.take<double>(static_cast<size_t>(L.nsplit) * n2);
+  if (mode != SINK_T_ONLY) {
+    z.template take<double>(static_cast<size_t>(L.nsplit) * n2);
+    z.template take<double>(static_cast<size_t>(L.nsplit) * n2);
   }
-  z.take<double>(n2);
-  z.take<double>((L.nmerge > L.ncolt ? L.nmerge : L.ncolt) + 1);
-  z.take<SinkCtl>(1);
-  z.take<double>(1);
+  z.template take<double>(n2);
+  z.template take<double>((L.nmerge > L.ncolt ? L.nmerge : L.ncolt) + 1);
+  z.template take<SinkCtl>(1);
+  z.template take<double>(1);
+  if (mode == SINK_FUSED) {
+    z.template take<uint64_t>(static_cast<size_t>(n1) * fuse_partners(n2));
+    z.template take<double>(static_cast<size_t>(fuse_groups_cap(n2)) * n2);
+  }
+}
+
+static size_t sink_scratch_bytes(int32_t n1, int32_t n2, SinkMode mode) {
+  Sizer z;
+  take_sink(z, n1, n2, mode);
   return z.off;
 }
 
-size_t sinkhorn_ws_bytes(int32_t n1, int32_t n2) { return sink_scratch_bytes(n1, n2, false); }
+size_t sinkhorn_ws_bytes(int32_t n1, int32_t n2, bool fused) {
+  return sink_scratch_bytes(n1, n2, fused ? SINK_FUSED : SINK_TWO_PASS);
+}
 
-static int carve_sink(Carver &cv, int32_t n1, int32_t n2, SinkWs &w, bool transposed_only) {
+static int carve_sink(Carver &cv, int32_t n1, int32_t n2, SinkWs &w, SinkMode mode) {
   SinkLayout L = sink_layout(n1, n2);
-  w.pm = transposed_only ? nullptr : cv.take<double>(static_cast<size_t>(L.nsplit) * n2);
-  w.ps = transposed_only ? nullptr : cv.take<double>(static_cast<size_t>(L.nsplit) * n2);
+  w.pm = mode == SINK_T_ONLY ? nullptr : cv.take<double>(static_cast<size_t>(L.nsplit) * n2);
+  w.ps = mode == SINK_T_ONLY ? nullptr : cv.take<double>(static_cast<size_t>(L.nsplit) * n2);
   w.a_next = cv.take<double>(n2);
   w.errp = cv.take<double>((L.nmerge > L.ncolt ? L.nmerge : L.ncolt) + 1);
   w.ctl = reinterpret_cast<int32_t *>(cv.take<SinkCtl>(1));
   w.err = cv.take<double>(1);
+  w.part = nullptr;
+  w.pcol = nullptr;
+  if (mode == SINK_FUSED) {
+    w.part = cv.take<uint64_t>(static_cast<size_t>(n1) * fuse_partners(n2));
+    w.pcol = cv.take<double>(static_cast<size_t>(fuse_groups_cap(n2)) * n2);
+  }
   w.nsplit = L.nsplit;
   w.nerrblk = L.nmerge;
   return cv.ok ? FA_OK : FA_ERR_WORKSPACE;
 }
 
-int carve_sinkhorn(Carver &cv, int32_t n1, int32_t n2, SinkWs &w) { return carve_sink(cv, n1, n2, w, false); }
+int carve_sinkhorn(Carver &cv, int32_t n1, int32_t n2, SinkWs &w, bool fused) {
+  return carve_sink(cv, n1, n2, w, fused ? SINK_FUSED : SINK_TWO_PASS);
+}
 
 // Vector store of V consecutive plan entries (one 16-byte FP32 or 8-byte BF16
 // store per lane for V = 4).
@@ -443,11 +501,17 @@ __global__ __launch_bounds__(256) void k_lse_col_t(const float *__restrict__ Ct,
   block_error(e, errp);
 }
 
-// Final a: copy the scratch buffer into the caller's a if it holds the result.
+// Final a: copy the scratch buffer into the caller's a if it holds the result.  After
+// an aborted single-pass iteration the outputs say so: iterations -1, error NaN.
 __global__ void k_final_a(double *__restrict__ a, const double *__restrict__ alt, int32_t n2,
-                          const SinkCtl *__restrict__ ctl) {
+                          const SinkCtl *__restrict__ ctl, int32_t *__restrict__ out_iters,
+                          double *__restrict__ out_err) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j == 0 && ctl->fault) {
+    *out_iters = -1;
+    *out_err = NAN;
+  }
   if (ctl->which != 1) return;
-  int j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j < n2) a[j] = alt[j];
 }
 
@@ -456,7 +520,382 @@ __global__ void k_sink_reset(SinkCtl *ctl) {
   ctl->iters = 0;
   ctl->which = 0;
   ctl->arrive = 0u;
+  ctl->fault = 0;
 }
+
+// ---------------------------------------------------------------- single-pass iteration
+
+// Exchange slots of the single pass: a partner's partial row sum (FP64, positive)
+// with its low 8 mantissa bits replaced by the pass tag (1..255; 0 = cleared), so
+// value and tag travel in one 64-bit word and a reader needs no ordering between
+// them: it polls a row's slots with device-scope atomic loads until every tag is
+// the current pass's.  Dropping 8 of 52 fraction bits changes the value by at most
+// 2^-44 relative.
+__device__ __forceinline__ uint64_t fuse_pack(double v, uint32_t tag) {
+  return (static_cast<uint64_t>(__double_as_longlong(v)) & ~0xffull) | tag;
+}
+__device__ __forceinline__ double fuse_value(uint64_t x) {
+  return __longlong_as_double(static_cast<long long>(x & ~0xffull));
+}
+
+// The rows of one row group, for one partner workgroup (one column slice), as a
+// pipeline over batches of K rows: load, then produce (2^y of the batch's entries,
+// its partial row sums published by wave 0), then consume (every wave forms the
+// batch's row sums over all partners itself, partner 0 updates b, and the batch's
+// plan entries go into the column sums).  Step t loads batch t+3, produces batch
+// t+2 and consumes batch t, so a batch's exchange has more than a step to complete
+// before it is needed.  ak (a_j log2(e)/eps of the slice; -inf for masked quads,
+// whose 2^y is then 0) and the column sums cs live in LDS, each thread owning its
+// entries.  A wave that gives up a wait records the fault and stops waiting but
+// runs to the end, so the workgroup's barriers stay matched.
+template <int Q, int K>
+struct FusePipe {
+  const float *C;
+  int32_t n2;
+  double k2, eps, log_mu, mu;
+  int32_t gc, c, spin_limit;
+  uint32_t tag;
+  int64_t row0, row1;
+  double *b;
+  uint64_t *part;
+  SinkCtl *ctl;
+  const double *ak;  // LDS [Q][256][4]
+  double *cs;        // LDS [Q][256][4]
+  double *bold;      // LDS [4][K]: the rows' b before the update, by batch mod 4
+  int jq[Q];
+  bool faulted;
+
+  __device__ __forceinline__ void load(int t, f32x4 (&x)[K][Q], double (&bx)[K]) const {
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      int64_t i = row0 + static_cast<int64_t>(t) * K + k;
+      if (i > row1 - 1) i = row1 - 1;  // rows past the group re-read its last row; they publish nothing
+#pragma unroll
+      for (int u = 0; u < Q; ++u) x[k][u] = ld_stream4(C + i * n2 + jq[u]);
+      bx[k] = b[i];
+    }
+  }
+
+  // 2^y of the batch (in place) and its partial row sums, published by wave 0.
+  __device__ __forceinline__ void produce(int t, f32x4 (&x)[K][Q], const double (&bx)[K], double (&red)[K][4]) const {
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    double sk[K];
+    double bk[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      sk[k] = 0.0;
+      bk[k] = bx[k] * k2;
+    }
+#pragma unroll
+    for (int u = 0; u < Q; ++u) {
+      double a4[4];
+#pragma unroll
+      for (int v = 0; v < 4; ++v) a4[v] = ak[(u * 256 + threadIdx.x) * 4 + v];
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        float q4 = 0.f;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          // y <= log2(nu_j) <= 0 after an a-update; below 2^-126 the result flushes to 0
+          const float e = __builtin_amdgcn_exp2f(static_cast<float>(fma(-static_cast<double>(x[k][u][v]), k2, a4[v] + bk[k])));
+          x[k][u][v] = e;
+          q4 += e;
+        }
+        sk[k] += static_cast<double>(q4);
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const double v = wave_sum(sk[k]);
+      if (lane == 0) red[k][wv] = v;
+    }
+    __syncthreads();
+    const int64_t ib = row0 + static_cast<int64_t>(t) * K;
+    if (threadIdx.x == 0)
+#pragma unroll
+      for (int k = 0; k < K; ++k) bold[(t & 3) * K + k] = bx[k];  // read when batch t is consumed
+    if (wv == 0 && lane < K && ib + lane < row1)
+      __hip_atomic_store(&part[(ib + lane) * gc + c],
+                         fuse_pack((red[lane][0] + red[lane][1]) + (red[lane][2] + red[lane][3]), tag),
+                         __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+
+  // This wave's snapshot of the batch's slots (lane l: row ib + l / gc, partner
+  // l mod gc; needs K * gc <= 64), loaded before the step's data loads so that
+  // reading it later does not wait for those (vector loads return in order).
+  // Lanes without a slot, and rows past the group, read as ready.  The read skips
+  // the CU's L1 and is served by the XCD's L2, where the stores of partners on the
+  // same XCD land (the grid puts a row group's partners on one XCD); it may miss a
+  // store from another XCD, but a stale slot carries an earlier pass's tag, so the
+  // batch then goes to the device-coherent gather.
+  __device__ __forceinline__ uint64_t snap(int64_t ib) const {
+    const int lane = threadIdx.x & 63;
+    if (lane >= K * gc || ib + lane / gc >= row1) return tag;
+    // rows ib .. ib+K-1 are consecutive, so lane's slot is ib * gc + lane: a uniform
+    // base plus the lane, with no per-lane address kept across the loop
+    return __hip_atomic_load(part + ib * gc + lane, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+  }
+
+  // Device-coherent gather (bounded wait): until every partner's slot of the
+  // batch's rows carries this pass's tag, then the row sums in partner order.
+  // After a wait is given up the fault is recorded and nothing more is awaited.
+  __device__ __forceinline__ void gather(int64_t ib, double (&rs)[K]) {
+    const int lane = threadIdx.x & 63;
+    int32_t spins = 0;
+    while (!faulted) {
+      bool ready = true;
+#pragma unroll
+      for (int k = 0; k < K; ++k)
+        if (ib + k < row1)
+          for (int q = lane; q < gc; q += 64)
+            ready &= (__hip_atomic_load(&part[(ib + k) * gc + q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) &
+                      0xffull) == tag;
+      if (__all(ready)) break;
+      ++spins;
+      if (spins > spin_limit ||
+          ((spins & 15) == 0 && __hip_atomic_load(&ctl->fault, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))) {
+        if (lane == 0) {
+          __hip_atomic_store(&ctl->fault, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          __hip_atomic_store(&ctl->done, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        faulted = true;
+      }
+      __builtin_amdgcn_s_sleep(1);
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      double v = 0.0;
+      if (ib + k < row1)
+        for (int q = lane; q < gc; q += 64)
+          v += fuse_value(__hip_atomic_load(&part[(ib + k) * gc + q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+      rs[k] = wave_sum(v);
+    }
+  }
+
+  // Row sums of batch t from all partners (this wave's snapshot if every tag in it
+  // is this pass's: a fixed butterfly within each row's gc lanes; else the gather),
+  // b (partner 0, wave 0), and the batch's plan entries into cs.
+  __device__ __forceinline__ void consume(int t, const f32x4 (&x)[K][Q], uint64_t x0) {
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int64_t ib = row0 + static_cast<int64_t>(t) * K;
+    double rs[K];
+    if (K * gc <= 64 && __all((x0 & 0xffull) == tag)) {
+      double v = lane < K * gc ? fuse_value(x0) : 0.0;
+      for (int o = 1; o < gc; o <<= 1) v += __shfl_xor(v, o, 64);  // gc is a power of two
+#pragma unroll
+      for (int k = 0; k < K; ++k) rs[k] = __shfl(v, k * gc < 64 ? k * gc : 0, 64);
+    } else {
+      gather(ib, rs);
+    }
+    // scale of 2^y to the plan after the b-update; kept in FP64 (as an FP32 factor its
+    // rounding would shift every entry of the row the same way)
+    double sg[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const bool valid = ib + k < row1;
+      sg[k] = valid ? mu / rs[k] : 0.0;
+      if (valid && c == 0 && wv == 0 && lane == 0) b[ib + k] = bold[(t & 3) * K + k] + eps * (log_mu - log(rs[k]));
+    }
+#pragma unroll
+    for (int u = 0; u < Q; ++u) {
+      double *cp = cs + (u * 256 + threadIdx.x) * 4;
+      double c4[4];
+#pragma unroll
+      for (int v = 0; v < 4; ++v) c4[v] = cp[v];
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+#pragma unroll
+        for (int k = 0; k < K; ++k) c4[v] = fma(static_cast<double>(x[k][u][v]), sg[k], c4[v]);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) cp[v] = c4[v];
+    }
+  }
+
+  // One pipeline step: snapshot batch t's slots, load batch t+3 into w, produce
+  // batch t+2 in y, consume batch t from x.  The compiler barriers keep the
+  // snapshot ahead of the data loads, and the loads are unconditional (past the
+  // group's end they re-read its last row; needs nb > 0): the same number of loads
+  // on every path lets the wait for the snapshot leave them in flight.  red is
+  // double-buffered by step parity: wave 0 may still read one step's partial sums
+  // while faster waves write the next step's.
+  __device__ __forceinline__ void step(int t, int nb, f32x4 (&x)[K][Q], double (&bx)[K], f32x4 (&y)[K][Q],
+                                       double (&by)[K], f32x4 (&w)[K][Q], double (&bw)[K], double (&red)[2][K][4]) {
+    uint64_t x0 = 0;
+    if (K * gc <= 64) x0 = snap(row0 + static_cast<int64_t>(t) * K);
+    asm volatile("" ::: "memory");
+    load(t + 3, w, bw);
+    asm volatile("" ::: "memory");
+    if (t + 2 < nb) produce(t + 2, y, by, red[t & 1]);
+    consume(t, x, x0);
+  }
+};
+
+// The single-pass iteration (b-update, then the column sums for the next
+// a-update) over rows [row0, row1) of a row group and one column slice.  The
+// grid is gr row groups x gc partners, all co-resident; with gr a multiple of 8
+// the partners of a row group are consecutive on one XCD (workgroup w runs on XCD
+// w mod 8), so their exchange stays in one L2.  Writes b (partner 0) and this
+// group's column sums pcol[r][j] of the plan after the b-update.
+template <int Q, int K>
+__global__ __launch_bounds__(256, 2) void k_sink_fused(const float *__restrict__ C, int32_t n1, int32_t n2,
+                                                       const double *__restrict__ bufA0,
+                                                       const double *__restrict__ bufA1, int32_t cur,
+                                                       double *__restrict__ b, double k2, double eps, double log_mu,
+                                                       double mu, int32_t gc, int32_t gr, uint32_t tag,
+                                                       uint64_t *__restrict__ part, double *__restrict__ pcol,
+                                                       SinkCtl *__restrict__ ctl, int32_t spin_limit) {
+  if (ctl->done) return;
+  const double *a = cur ? bufA1 : bufA0;
+  const int w = blockIdx.x;
+  int r, c;
+  if (gr % 8 == 0) {
+    const int l = w >> 3;
+    r = (w & 7) * (gr >> 3) + l / gc;
+    c = l % gc;
+  } else {
+    r = w / gc;
+    c = w % gc;
+  }
+  __shared__ double ak[Q * 256 * 4];
+  __shared__ double cs[Q * 256 * 4];
+  __shared__ double red[2][K][4];
+  __shared__ double bold[4 * K];
+  FusePipe<Q, K> F;
+  F.C = C;
+  F.n2 = n2;
+  F.k2 = k2;
+  F.eps = eps;
+  F.log_mu = log_mu;
+  F.mu = mu;
+  F.gc = gc;
+  F.c = c;
+  F.tag = tag;
+  F.spin_limit = spin_limit;
+  F.row0 = static_cast<int64_t>(r) * n1 / gr;
+  F.row1 = static_cast<int64_t>(r + 1) * n1 / gr;
+  F.b = b;
+  F.part = part;
+  F.ctl = ctl;
+  F.ak = ak;
+  F.cs = cs;
+  F.bold = bold;
+  F.faulted = false;
+  const int nb = static_cast<int>((F.row1 - F.row0 + K - 1) / K);
+  const int nq = n2 >> 2;
+  const int q0 = static_cast<int>(static_cast<int64_t>(c) * nq / gc);
+  const int q1 = static_cast<int>(static_cast<int64_t>(c + 1) * nq / gc);
+  bool qv[Q];
+#pragma unroll
+  for (int u = 0; u < Q; ++u) {
+    const int q = q0 + static_cast<int>(threadIdx.x) + 256 * u;
+    qv[u] = q < q1;
+    F.jq[u] = 4 * (q < q1 ? q : (q1 > q0 ? q1 - 1 : 0));  // masked quads re-read a valid one
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      ak[(u * 256 + threadIdx.x) * 4 + v] = qv[u] ? a[F.jq[u] + v] * k2 : -INFINITY;
+      cs[(u * 256 + threadIdx.x) * 4 + v] = 0.0;
+    }
+  }
+  __syncthreads();
+  if (nb > 0) {
+    f32x4 x0[K][Q], x1[K][Q], x2[K][Q], x3[K][Q];
+    double b0[K], b1[K], b2[K], b3[K];
+    F.load(0, x0, b0);
+    F.load(1, x1, b1);
+    F.load(2, x2, b2);
+    F.produce(0, x0, b0, red[0]);
+    if (nb > 1) F.produce(1, x1, b1, red[1]);
+    for (int t = 0; t < nb; t += 4) {
+      F.step(t, nb, x0, b0, x2, b2, x3, b3, red);
+      if (t + 1 >= nb) break;
+      F.step(t + 1, nb, x1, b1, x3, b3, x0, b0, red);
+      if (t + 2 >= nb) break;
+      F.step(t + 2, nb, x2, b2, x0, b0, x1, b1, red);
+      if (t + 3 >= nb) break;
+      F.step(t + 3, nb, x3, b3, x1, b1, x2, b2, red);
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < Q; ++u)
+    if (qv[u])
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+        pcol[static_cast<int64_t>(r) * n2 + F.jq[u] + v] = cs[(u * 256 + threadIdx.x) * 4 + v];
+}
+
+// Column sums of the plan after the b-update: fold the gr row-group sums of each
+// column in order, form the candidate a_j (into the other buffer) and the column's
+// marginal violation; k_error_finish then forms the total and applies the stop rule.
+__global__ __launch_bounds__(256) void k_fused_merge(int32_t n2, int32_t gr, const double *__restrict__ pcol,
+                                                     double *__restrict__ bufA0, double *__restrict__ bufA1,
+                                                     int32_t cur, double eps, double log_nu, double nu,
+                                                     double *__restrict__ errp, const SinkCtl *__restrict__ ctl) {
+  if (ctl->done) return;
+  const double *a = cur ? bufA1 : bufA0;
+  double *an = cur ? bufA0 : bufA1;
+  const int j = blockIdx.x * 256 + threadIdx.x;
+  double e = 0.0;
+  if (j < n2) {
+    double sum = 0.0;
+    for (int q = 0; q < gr; ++q) sum += pcol[static_cast<int64_t>(q) * n2 + j];
+    an[j] = a[j] + eps * (log_nu - log(sum));
+    e = fabs(sum - nu);
+  }
+  block_error(e, errp);
+}
+
+// Grid of the single-pass iteration on the current device: gc partners per row,
+// gr row groups, every workgroup co-resident (occupancy x compute units, looked up
+// once per device).  FA_ERR_SHAPE when the shape or the device does not allow it.
+struct FuseGrid {
+  int gc, gr;
+};
+
+namespace {
+constexpr int kMaxDev = 64;
+std::mutex g_fuse_mu;
+int g_fuse_slots[kMaxDev] = {};
+}  // namespace
+
+static int fuse_slots(int *slots) {
+  int dev = -1;
+  FA_HIP(hipGetDevice(&dev));
+  FA_REQUIRE(dev >= 0 && dev < kMaxDev, FA_ERR_ARG, "single-pass Sinkhorn: device %d out of range", dev);
+  std::lock_guard<std::mutex> lock(g_fuse_mu);
+  if (!g_fuse_slots[dev]) {
+    int per_cu = 0, cus = 0, coop = 0;
+    FA_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(
+        &per_cu, reinterpret_cast<const void *>(&k_sink_fused<kFuseQ, kFuseK>), 256, 0));
+    FA_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    FA_HIP(hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev));
+    const int64_t n = coop ? static_cast<int64_t>(per_cu) * cus : 0;
+    g_fuse_slots[dev] = static_cast<int>(n < kFuseMaxGrid ? n : kFuseMaxGrid);
+    if (!g_fuse_slots[dev]) g_fuse_slots[dev] = -1;
+  }
+  *slots = g_fuse_slots[dev];
+  return FA_OK;
+}
+
+static int fuse_grid(int32_t n1, int32_t n2, FuseGrid *g) {
+  FA_REQUIRE(n1 > 0 && n2 > 0 && n2 % 4 == 0, FA_ERR_SHAPE,
+             "single-pass Sinkhorn: n2 = %d must be a positive multiple of 4", n2);
+  int slots = 0;
+  FA_TRY(fuse_slots(&slots));
+  const int gc = fuse_partners(n2);
+  FA_REQUIRE(slots > 0 && gc <= slots && gc <= n2 / 4, FA_ERR_SHAPE,
+             "single-pass Sinkhorn: %d partners per row do not fit %d co-resident workgroups", gc, slots);
+  int64_t gr = slots / gc;
+  const int64_t cap = fuse_groups_cap(n2);
+  const int64_t rows = (static_cast<int64_t>(n1) + kFuseK - 1) / kFuseK;
+  if (gr > cap) gr = cap;
+  if (gr > rows) gr = rows;
+  if (gr >= 8) gr -= gr % 8;
+  g->gc = gc;
+  g->gr = static_cast<int>(gr);
+  return FA_OK;
+}
+
+std::atomic<int32_t> g_fuse_spin{kFuseSpinDefault};
 
 int run_sinkhorn(const float *C, const float *Ct, int32_t n1, int32_t n2, double eps, double *a, double *b,
                  int32_t max_iter, double tol, int32_t check_every, int32_t *dev_iters, double *dev_err, SinkWs &w,
@@ -468,10 +907,44 @@ int run_sinkhorn(const float *C, const float *Ct, int32_t n1, int32_t n2, double
   const double log_mu = -log(static_cast<double>(n1));
   FA_LAUNCH(k_sink_reset, dim3(1), dim3(1), 0, s, ctl);
   const dim3 gcol(L.ncolblk, L.nsplit), gmerge(L.nmerge), grow(ceil_div(n1, kRowsPerWg));
+  // Single-pass form: iterations 0 and 1 run the two passes (iteration 0's b-update
+  // makes every row sum of the plan mu_i, which bounds the row sums the single pass
+  // sees from iteration 2 on), then one pass per iteration.
+  FuseGrid fg{0, 0};
+  const bool fused = w.part != nullptr && max_iter >= 2 && fuse_grid(n1, n2, &fg) == FA_OK;
+  // clear the exchange slots (tag 0 is never a pass's tag)
+  if (fused)
+    FA_TRY(launch_fill_f64(reinterpret_cast<double *>(w.part), static_cast<int64_t>(n1) * fg.gc, 0.0, s));
+  const double mu = 1.0 / n1;
+  const int32_t spin = g_fuse_spin.load();
   for (int it = 0; it <= max_iter; ++it) {
     const int cur = it & 1;
     const int is_final = it == max_iter;
     const int is_check = it > 0 && (it % check_every == 0);
+    if (fused && it >= 2) {
+      const float *cC = C;
+      int32_t cn1 = n1, cn2 = n2, ccur = cur, gc = fg.gc, gr = fg.gr, sp = spin;
+      uint32_t tag = static_cast<uint32_t>((it - 2) % 255 + 1);  // consecutive passes never share a tag
+      const double *ca0 = a, *ca1 = w.a_next;
+      double *cb = b, *cpcol = w.pcol;
+      uint64_t *cpart = w.part;
+      double ck2 = k2, ceps = eps, clog_mu = log_mu, cmu = mu;
+      SinkCtl *cctl = ctl;
+      void *args[] = {&cC, &cn1, &cn2, &ca0, &ca1, &ccur, &cb, &ck2, &ceps, &clog_mu, &cmu, &gc, &gr, &tag,
+                      &cpart, &cpcol, &cctl, &sp};
+      FA_TIMED(tm, KK_FUSED, s,
+               FA_HIP(hipLaunchCooperativeKernel(reinterpret_cast<const void *>(&k_sink_fused<kFuseQ, kFuseK>),
+                                                 dim3(fg.gr * fg.gc), dim3(256), args, 0, s)));
+      const int nm = ceil_div(n2, 256);
+      FA_TIMED(tm, KK_COL_MERGE, s,
+               FA_LAUNCH(k_fused_merge, dim3(nm), dim3(256), 0, s, n2, fg.gr, w.pcol, a, w.a_next, cur, eps, log_nu, nu,
+                         w.errp, ctl));
+      FA_TIMED(tm, KK_COL_MERGE, s,
+               FA_LAUNCH(k_error_finish, dim3(1), dim3(256), 0, s, w.errp, nm, ctl, it, is_check, is_final, tol, cur,
+                         dev_iters, dev_err));
+      if (is_final) break;
+      continue;
+    }
     if (Ct) {
       const dim3 gct(L.ncolt);
       if (n1 % 4 == 0)
@@ -499,6 +972,7 @@ int run_sinkhorn(const float *C, const float *Ct, int32_t n1, int32_t n2, double
                          log_nu, nu, w.errp, ctl, it, is_check, is_final, tol, dev_iters, dev_err));
     }
     if (is_final) break;
+    if (fused && it == 1) continue;  // iteration 2's b-update is the first single pass
     if (L.V == 4)
       FA_TIMED(tm, KK_ROW, s,
                FA_LAUNCH((k_lse_row<4, kRowsPerWg>), grow, dim3(256), 0, s, C, n1, n2, a, w.a_next, 1 - cur, b, k2, eps, log_mu,
@@ -508,7 +982,7 @@ int run_sinkhorn(const float *C, const float *Ct, int32_t n1, int32_t n2, double
                FA_LAUNCH((k_lse_row<1, kRowsPerWg>), grow, dim3(256), 0, s, C, n1, n2, a, w.a_next, 1 - cur, b, k2, eps, log_mu,
                          ctl));
   }
-  FA_LAUNCH(k_final_a, dim3(ceil_div(n2, 256)), dim3(256), 0, s, a, w.a_next, n2, ctl);
+  FA_LAUNCH(k_final_a, dim3(ceil_div(n2, 256)), dim3(256), 0, s, a, w.a_next, n2, ctl, dev_iters, dev_err);
   return FA_OK;
 }
 
@@ -639,13 +1113,64 @@ int run_plan(const float *C, int32_t n1, int32_t n2, double eps, const double *a
   return FA_OK;
 }
 
+int sinkhorn_fault(const SinkWs &w, hipStream_t s, int32_t *fault) {
+  SinkCtl c;
+  FA_HIP(hipMemcpyAsync(&c, w.ctl, sizeof c, hipMemcpyDeviceToHost, s));
+  FA_HIP(hipStreamSynchronize(s));
+  *fault = c.fault;
+  return FA_OK;
+}
+
 }  // namespace fa
 
 using namespace fa;
 
 extern "C" size_t fa_sinkhorn_workspace_size(int32_t n1, int32_t n2) {
   if (n1 <= 0 || n2 <= 0) return 256;
-  return sinkhorn_ws_bytes(n1, n2);
+  return sinkhorn_ws_bytes(n1, n2, false);
+}
+
+extern "C" size_t fa_sinkhorn_fused_workspace_size(int32_t n1, int32_t n2) {
+  if (n1 <= 0 || n2 <= 0) return 256;
+  return sinkhorn_ws_bytes(n1, n2, true);
+}
+
+extern "C" int fa_sinkhorn_fused_grid(int32_t n1, int32_t n2, int32_t *gr, int32_t *gc) {
+  FA_REQUIRE(gr && gc, FA_ERR_ARG, "fa_sinkhorn_fused_grid: null output");
+  FuseGrid g;
+  FA_TRY(fuse_grid(n1, n2, &g));
+  *gr = g.gr;
+  *gc = g.gc;
+  return FA_OK;
+}
+
+extern "C" int32_t fa_set_sync_spin_limit(int32_t polls) {
+  return g_fuse_spin.exchange(polls < 1 ? 1 : polls);
+}
+
+extern "C" int fa_sinkhorn_fused(const float *C, int32_t n1, int32_t n2, double eps, double *a, double *b,
+                                 int32_t max_iter, double tol, int32_t check_every, int32_t *dev_iters,
+                                 double *dev_err, int32_t *host_iters, double *host_err, void *ws, size_t ws_bytes,
+                                 void *stream) {
+  FA_REQUIRE(n1 > 0 && n2 > 0, FA_ERR_SHAPE, "fa_sinkhorn_fused: n1 = %d, n2 = %d must be positive", n1, n2);
+  FA_REQUIRE(eps > 0 && max_iter >= 0 && check_every >= 1 && tol >= 0, FA_ERR_ARG,
+             "fa_sinkhorn_fused: need eps > 0, max_iter >= 0, check_every >= 1, tol >= 0");
+  FA_REQUIRE(C && a && b && dev_iters && dev_err, FA_ERR_ARG, "fa_sinkhorn_fused: null pointer");
+  const size_t need = sinkhorn_ws_bytes(n1, n2, true);
+  FA_REQUIRE(ws && ws_bytes >= need, FA_ERR_WORKSPACE, "fa_sinkhorn_fused: workspace %zu < %zu", ws_bytes, need);
+  Carver cv(ws, ws_bytes);
+  SinkWs w;
+  FA_TRY(carve_sinkhorn(cv, n1, n2, w, true));
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  FA_TRY(run_sinkhorn(C, nullptr, n1, n2, eps, a, b, max_iter, tol, check_every, dev_iters, dev_err, w, s));
+  if (host_iters || host_err) {
+    int32_t fault = 0;
+    FA_TRY(sinkhorn_fault(w, s, &fault));
+    FA_REQUIRE(!fault, FA_ERR_SYNC, "fa_sinkhorn_fused: a partner wait of the single pass gave up");
+    if (host_iters) FA_HIP(hipMemcpy(host_iters, dev_iters, sizeof(int32_t), hipMemcpyDeviceToHost));
+    if (host_err) FA_HIP(hipMemcpy(host_err, dev_err, sizeof(double), hipMemcpyDeviceToHost));
+  }
+  return FA_OK;
 }
 
 extern "C" int fa_sinkhorn(const float *C, const float *Ct, int32_t n1, int32_t n2, double eps, double *a, double *b,
@@ -655,11 +1180,11 @@ extern "C" int fa_sinkhorn(const float *C, const float *Ct, int32_t n1, int32_t 
   FA_REQUIRE(eps > 0 && max_iter >= 0 && check_every >= 1 && tol >= 0, FA_ERR_ARG,
              "fa_sinkhorn: need eps > 0, max_iter >= 0, check_every >= 1, tol >= 0");
   FA_REQUIRE(C && a && b && dev_iters && dev_err, FA_ERR_ARG, "fa_sinkhorn: null pointer");
-  FA_REQUIRE(ws && ws_bytes >= sinkhorn_ws_bytes(n1, n2), FA_ERR_WORKSPACE, "fa_sinkhorn: workspace %zu < %zu",
-             ws_bytes, sinkhorn_ws_bytes(n1, n2));
+  FA_REQUIRE(ws && ws_bytes >= sinkhorn_ws_bytes(n1, n2, false), FA_ERR_WORKSPACE,
+             "fa_sinkhorn: workspace %zu < %zu", ws_bytes, sinkhorn_ws_bytes(n1, n2, false));
   Carver cv(ws, ws_bytes);
   SinkWs w;
-  FA_TRY(carve_sinkhorn(cv, n1, n2, w));
+  FA_TRY(carve_sinkhorn(cv, n1, n2, w, false));
   hipStream_t s = static_cast<hipStream_t>(stream);
   FA_TRY(run_sinkhorn(C, Ct, n1, n2, eps, a, b, max_iter, tol, check_every, dev_iters, dev_err, w, s));
   if (host_iters || host_err) {
@@ -711,7 +1236,7 @@ int device_scratch(void **out) {
 
 extern "C" size_t fa_sinkhorn_noalloc_need(int32_t n1, int32_t n2, int32_t transposed) {
   if (n1 <= 0 || n2 <= 0) return 0;
-  return sink_scratch_bytes(n1, n2, transposed != 0);
+  return sink_scratch_bytes(n1, n2, transposed != 0 ? SINK_T_ONLY : SINK_TWO_PASS);
 }
 
 extern "C" int fa_sinkhorn_noalloc(const float *C, const float *Ct, int32_t n1, int32_t n2, double eps, double *a,
@@ -722,7 +1247,7 @@ extern "C" int fa_sinkhorn_noalloc(const float *C, const float *Ct, int32_t n1, 
              "fa_sinkhorn_noalloc: need eps > 0, max_iter >= 0, check_every >= 1, tol >= 0");
   FA_REQUIRE(C && a && b && dev_iters && dev_err, FA_ERR_ARG, "fa_sinkhorn_noalloc: null pointer");
   const bool tr = Ct != nullptr;
-  const size_t need = sink_scratch_bytes(n1, n2, tr);
+  const size_t need = sink_scratch_bytes(n1, n2, tr ? SINK_T_ONLY : SINK_TWO_PASS);
   FA_REQUIRE(need <= FA_SINKHORN_NOALLOC_SCRATCH, FA_ERR_SHAPE,
              "fa_sinkhorn_noalloc: %d x %d needs %zu bytes of scratch %s, the static array holds %zu "
              "(use fa_sinkhorn with a workspace)",
@@ -732,7 +1257,7 @@ extern "C" int fa_sinkhorn_noalloc(const float *C, const float *Ct, int32_t n1, 
   FA_TRY(device_scratch(&ptr));
   Carver cv(ptr, FA_SINKHORN_NOALLOC_SCRATCH);
   SinkWs w;
-  FA_TRY(carve_sink(cv, n1, n2, w, tr));
+  FA_TRY(carve_sink(cv, n1, n2, w, tr ? SINK_T_ONLY : SINK_TWO_PASS));
   return run_sinkhorn(C, Ct, n1, n2, eps, a, b, max_iter, tol, check_every, dev_iters, dev_err, w,
                       static_cast<hipStream_t>(stream));
 }

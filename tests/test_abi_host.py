@@ -100,7 +100,7 @@ C_CONSUMER = r"""
 int main(void) {
   fa_params p;
   fa_default_params(&p);
-  if (!(p.eps > 0.0) || p.transpose_cost != 1 || p.plan_in_ct != 0) return 2;
+  if (!(p.eps > 0.0) || p.transpose_cost != 0 || p.plan_in_ct != 0 || p.sink_fused != 1) return 2;
   /* triangle 0-1-2 plus a pendant 3-2, a loop and a duplicate */
   const int64_t e[] = {0, 1, 1, 2, 2, 0, 3, 2, 1, 1, 1, 0};
   int64_t rowptr[5], nnz = -1;

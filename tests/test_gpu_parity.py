@@ -261,16 +261,31 @@ def test_cost_per_term(api, case, terms, sdt):
         assert torch.equal(CT.view(torch.int32), C2.t().contiguous().view(torch.int32))
 
 
+def _sink(api, C, eps, a, b, max_iter, form, tol=0.0, check_every=1):
+    """One of the three forms of the inner solve: column strips, rows of C^T, or the
+    single pass (which falls back to two passes where its shape is not allowed)."""
+    if form == "fused":
+        return api.sinkhorn_fused(C, eps, a, b, max_iter, tol=tol, check_every=check_every)
+    return api.sinkhorn(C, eps, a, b, max_iter, tol=tol, check_every=check_every,
+                        Ct=C.t().contiguous() if form == "transposed" else None)
+
+
+SINK_FORMS = ["strips", "transposed", "fused"]
+
+
 def _sinkhorn_case(n1, n2, seed, eps):
     r = np.random.default_rng(seed)
     C = 10.0 + r.random((n1, n2)) * 2.0 + np.add.outer(r.random(n1), r.random(n2)) * 5.0
     return C
 
 
-@pytest.mark.parametrize("transposed", [False, True], ids=["strips", "transposed"])
-@pytest.mark.parametrize("shape", [(600, 2500), (513, 301), (1, 7), (9, 1), (300, 2503), (2503, 300)])
-def test_sinkhorn_fixed_iterations(api, shape, transposed):
-    """Both column passes (strips of C, or rows of C^T); odd sizes take the scalar paths."""
+@pytest.mark.parametrize("form", SINK_FORMS)
+@pytest.mark.parametrize("shape", [(600, 2500), (513, 301), (1, 7), (9, 1), (300, 2503), (2503, 300), (2050, 4100),
+                                   (300, 8200), (129, 20004), (3, 16388)])
+def test_sinkhorn_fixed_iterations(api, shape, form):
+    """All column passes (strips of C, rows of C^T, the single pass); odd sizes take
+    the scalar paths; n2 > 4096 splits each row of the single pass over 2, 4 or 8
+    partner workgroups, and n1 = 3 leaves most row groups of its grid empty."""
     n1, n2 = shape
     eps = 0.05
     C = _sinkhorn_case(n1, n2, n1 + n2, eps)
@@ -279,7 +294,7 @@ def test_sinkhorn_fixed_iterations(api, shape, transposed):
     Ct = torch.from_numpy(C32).cuda()
     a = torch.zeros(n2, dtype=torch.float64, device="cuda")
     b = torch.zeros(n1, dtype=torch.float64, device="cuda")
-    it, err = api.sinkhorn(Ct, eps, a, b, 25, Ct=Ct.t().contiguous() if transposed else None)
+    it, err = _sink(api, Ct, eps, a, b, 25, form)
     assert it == 25 == it_o
     S_o = O.plan(C32.astype(np.float64), a_o, b_o, eps)
     S_g = O.plan(C32.astype(np.float64), a.cpu().numpy(), b.cpu().numpy(), eps)
@@ -291,23 +306,23 @@ def test_sinkhorn_fixed_iterations(api, shape, transposed):
     assert abs(err - err_o) <= 1e-6 + 1e-3 * err_o
 
 
-@pytest.mark.parametrize("transposed", [False, True], ids=["strips", "transposed"])
-def test_sinkhorn_two_by_two_closed_form(api, transposed):
+@pytest.mark.parametrize("form", SINK_FORMS)
+def test_sinkhorn_two_by_two_closed_form(api, form):
     for delta, eps in [(0.3, 0.1), (-1.0, 0.25)]:
         C = torch.tensor([[delta, 0.0], [0.0, 0.0]], dtype=torch.float32, device="cuda")
         a = torch.zeros(2, dtype=torch.float64, device="cuda")
         b = torch.zeros(2, dtype=torch.float64, device="cuda")
         # the GPU evaluates the marginal error with FP32 exponentials of FP64-shifted
         # exponents: its resolution is ~2^-24 * |shift| * ln 2 relative per entry
-        it, err = api.sinkhorn(C, eps, a, b, 3000, tol=1e-7, Ct=C.t().contiguous() if transposed else None)
+        it, err = _sink(api, C, eps, a, b, 3000, form, tol=1e-7)
         S = api.plan(C, eps, a, b).cpu().numpy()
         x = 1.0 / (2.0 * (1.0 + math.exp(delta / (2 * eps))))
         assert np.allclose(S, [[x, 0.5 - x], [0.5 - x, x]], atol=2e-7)
         assert err <= 1e-7 and it < 3000
 
 
-@pytest.mark.parametrize("transposed", [False, True], ids=["strips", "transposed"])
-def test_sinkhorn_tolerance_stop_matches_oracle(api, transposed):
+@pytest.mark.parametrize("form", SINK_FORMS)
+def test_sinkhorn_tolerance_stop_matches_oracle(api, form):
     n1, n2, eps = 200, 300, 0.2
     C = _sinkhorn_case(n1, n2, 3, eps) * 0.2
     C32 = C.astype(np.float32).astype(np.float64)
@@ -316,12 +331,69 @@ def test_sinkhorn_tolerance_stop_matches_oracle(api, transposed):
     Ct = T32(C32)
     a = torch.zeros(n2, dtype=torch.float64, device="cuda")
     b = torch.zeros(n1, dtype=torch.float64, device="cuda")
-    it, err = api.sinkhorn(Ct, eps, a, b, 5000, tol=tol, check_every=1, Ct=Ct.t().contiguous() if transposed else None)
+    it, err = _sink(api, Ct, eps, a, b, 5000, form, tol=tol)
     assert err <= tol and abs(it - it_o) <= 1, (it, it_o, err, err_o)
     # marginal error evaluated independently in FP64 from the returned duals
     S = O.plan(C32, a.cpu().numpy(), b.cpu().numpy(), eps)
     assert np.abs(S.sum(0) - 1 / n2).sum() <= 2 * tol
     assert np.abs(S.sum(1) - 1 / n1).sum() <= 1e-7   # rows exact up to the FP32-exp resolution
+
+
+@pytest.mark.parametrize("shape", [(700, 8200), (257, 4100), (2503, 2500)])
+def test_sinkhorn_single_pass_matches_two_pass(api, shape):
+    """The single pass runs the same iteration as the two-pass loop: with a tolerance
+    and a check every 7 iterations both stop at the same check, and the duals, the
+    reported error and the plan agree to summation order."""
+    n1, n2 = shape
+    eps = 0.1
+    C = T32(_sinkhorn_case(n1, n2, 11 + n1, eps) * 0.3)
+    assert api.sinkhorn_fused_grid(n1, n2) is not None
+    out = {}
+    for form in ("transposed", "fused"):
+        a = torch.zeros(n2, dtype=torch.float64, device="cuda")
+        b = torch.zeros(n1, dtype=torch.float64, device="cuda")
+        it, err = _sink(api, C, eps, a, b, 400, form, tol=1e-5, check_every=7)
+        out[form] = (it, err, a, b)
+    (i1, e1, a1, b1), (i2, e2, a2, b2) = out["transposed"], out["fused"]
+    assert i1 == i2 and i1 % 7 == 0 and i1 < 400, (i1, i2)
+    # the error measure resolves about 2^-24 relative per column sum (FP32 exponentials),
+    # i.e. ~1e-7 in total over the columns: below that the two values are rounding noise
+    assert abs(e1 - e2) <= 1e-3 * max(e1, e2) + 1e-7, (e1, e2)
+    # FP32 exponentials in both forms (relative 2^-24 per entry, differently shifted): the
+    # oracle bar of the fixed-iteration test, 1e-5 eps on the duals and on the plan
+    assert float((a1 - a2).abs().max()) <= 1e-5 * eps and float((b1 - b2).abs().max()) <= 1e-5 * eps
+    S1, S2 = api.plan(C, eps, a1, b1), api.plan(C, eps, a2, b2)
+    assert float((S1 - S2).abs().max()) <= 1e-5 * float(S1.max())
+
+
+def test_sinkhorn_single_pass_gives_up_a_bounded_wait(api):
+    """The partners' waits are bounded: with the bound forced down to one poll from
+    the host, some wait gives up, every workgroup leaves the pass, the call reports
+    FA_ERR_SYNC and the device outputs say so (iterations -1, error NaN).  With the
+    bound restored the same call succeeds on the same workspace-free inputs."""
+    import ctypes as Cc
+    from paper_2607_11952_amd import binding
+    lib = binding.load()
+    n1, n2, eps = 4000, 16388, 0.1
+    assert api.sinkhorn_fused_grid(n1, n2)[1] >= 4
+    C = T32(_sinkhorn_case(n1, n2, 5, eps) * 0.3)
+    a = torch.zeros(n2, dtype=torch.float64, device="cuda")
+    b = torch.zeros(n1, dtype=torch.float64, device="cuda")
+    prev = lib.raw("fa_set_sync_spin_limit")(1)
+    try:
+        with pytest.raises(binding.FastAlignError) as ex:
+            api.sinkhorn_fused(C, eps, a, b, 40)
+        assert ex.value.status == binding.FA_ERR_SYNC
+    finally:
+        assert lib.raw("fa_set_sync_spin_limit")(prev) == 1
+    a.zero_()
+    b.zero_()
+    it, err = api.sinkhorn_fused(C, eps, a, b, 40)
+    a2 = torch.zeros_like(a)
+    b2 = torch.zeros_like(b)
+    it2, err2 = api.sinkhorn(C, eps, a2, b2, 40)
+    assert it == it2 == 40 and abs(err - err2) <= 1e-3 * err2 + 1e-7
+    assert float((a - a2).abs().max()) <= 1e-5 * eps
 
 
 @pytest.mark.parametrize("n2", [2500, 301])
@@ -390,14 +462,15 @@ def _plan_close(S_gpu, S_ref, bound):
     return _plan_err(S_gpu, S_ref) <= bound
 
 
-@pytest.mark.parametrize("transpose_cost", [1, 0], ids=["transposed", "strips"])
-def test_align_small_config_end_to_end(api, transpose_cost):
+@pytest.mark.parametrize("sink_fused,transpose_cost", [(1, 0), (0, 1), (0, 0)], ids=["fused", "transposed", "strips"])
+def test_align_small_config_end_to_end(api, sink_fused, transpose_cost):
     """The small workload (ER n=1000, eps 0.05, 10 x 50): plan within 1e-4, argmax identical,
-    with either column pass."""
+    with each form of the inner solve (the single pass; two passes over rows of C^T or
+    column strips of C)."""
     cfg = CONFIGS["er1k"]
     pr = make_pair(cfg)
     p = O.Params(eps=cfg.eps, outer_iters=cfg.outer_iters, inner_iters=cfg.inner_iters)
-    ref, res = _align_both(api, pr, p, transpose_cost=transpose_cost)
+    ref, res = _align_both(api, pr, p, transpose_cost=transpose_cost, sink_fused=sink_fused)
     S = _np(res.S)
     assert _plan_close(S, ref["S"], 1e-4), np.abs(S - ref["S"]).max() / ref["S"].max()
     assert np.array_equal(_np(res.argmax), ref["argmax"])
@@ -572,9 +645,9 @@ def test_align_degenerate_inputs(api, kind, plan_in_ct, monkeypatch):
         assert np.all(ref["argmax"] == 0) and np.ptp(ref["S"]) <= 1e-12 * ref["S"].max()
 
 
-@pytest.mark.parametrize("transposed", [False, True], ids=["strips", "transposed"])
+@pytest.mark.parametrize("form", SINK_FORMS)
 @pytest.mark.parametrize("shape", [(1, 5), (300, 257), (64, 1), (129, 1030)])
-def test_sinkhorn_additive_cost_at_large_magnitude(api, shape, transposed):
+def test_sinkhorn_additive_cost_at_large_magnitude(api, shape, form):
     """C_ij = u_i + v_j with |u|, |v| up to 1000 and eps = 0.01 (exponents up to
     2e5, far outside FP32's range): one iteration of Eq. (3) from zero duals gives
     a_j = v_j + eps log nu - eps L and b_i = u_i + eps log mu + eps L with
@@ -591,7 +664,7 @@ def test_sinkhorn_additive_cost_at_large_magnitude(api, shape, transposed):
     Cd = torch.from_numpy(C).cuda()
     a = torch.zeros(n2, dtype=torch.float64, device=Cd.device)
     b = torch.zeros(n1, dtype=torch.float64, device=Cd.device)
-    it, err = api.sinkhorn(Cd, eps, a, b, 1, Ct=Cd.t().contiguous() if transposed else None)
+    it, err = _sink(api, Cd, eps, a, b, 1, form)
     L = logsumexp(-u / eps)
     a_want = v + eps * np.log(1.0 / n2) - eps * L
     b_want = u + eps * np.log(1.0 / n1) + eps * L

@@ -77,14 +77,14 @@ def _pair_cases():
 def test_align_plan_in_ct_is_identical(api, cfg, form):
     """The working plan kept in the C^T buffer (the rebuild writes C only, a transpose
     pass regenerates C^T) gives bit-identical duals, plan, argmax and ranks to the
-    run with a dense plan buffer; without any dense plan the top-k lists and ranks
-    agree with that plan."""
+    run with a dense plan buffer (both keep C^T, so their inner solves run the same
+    passes); without any dense plan the top-k lists and ranks agree with that plan."""
     pr = make_pair(cfg)
     truth = pr.truth.astype(np.int32).copy()
     truth[pr.anchors[:, 0]] = -1
     tt = torch.from_numpy(truth).cuda()
     inp = api.AlignInputs.from_pair(pr)
-    kw = dict(eps=0.05, outer_iters=4, inner_iters=30, plan_dtype=form, feat_dtype=form)
+    kw = dict(eps=0.05, outer_iters=4, inner_iters=30, plan_dtype=form, feat_dtype=form, transpose_cost=1)
     ref = api.align(inp, api.params(**kw), truth=tt)
     sh = api.align(inp, api.params(plan_in_ct=1, **kw), truth=tt)
     for f in ("S", "a", "b", "argmax", "rank"):
