@@ -106,6 +106,7 @@ static void size_group(void) {
     for (int j = 0; j < 6; ++j) {
       int32_t n1 = n1s[i], n2 = n2s[j];
       CHECK(fa_sinkhorn_workspace_size(n1, n2) > 0);
+      CHECK(fa_sinkhorn_fused_workspace_size(n1, n2) > fa_sinkhorn_workspace_size(n1, n2));
       CHECK(fa_sinkhorn_noalloc_need(n1, n2, 1) > 0);
       CHECK(fa_sinkhorn_noalloc_need(n1, n2, 0) >= fa_sinkhorn_noalloc_need(n1, n2, 1));
       for (int dt = 0; dt < 2; ++dt) {
@@ -120,6 +121,7 @@ static void size_group(void) {
         q.transpose_cost = (opt & 4) ? 1 : 0;
         q.plan_in_ct = (opt & 8) && q.transpose_cost;
         q.warm_start = (opt & 16) ? 1 : 0;
+        q.sink_fused = (opt & 1) ^ ((opt >> 2) & 1);
         for (int ds = 0; ds < 3; ++ds) {
           q.dual_start = ds;
           size_t w = fa_align_workspace_size(n1, n2, 32, 10, 8LL * n1, 8LL * n2, &q);
@@ -173,6 +175,16 @@ static void arg_group(void) {
   CHECK(fa_sinkhorn(dummy, NULL, 4, 4, 0.1, da, da, 10, 0, 1, di, da, NULL, NULL, NULL, 0, NULL) ==
         FA_ERR_WORKSPACE);
   CHECK(fa_sinkhorn_noalloc(dummy, NULL, 64, 3000000, 0.1, da, da, 10, 0, 1, di, da, NULL) == FA_ERR_SHAPE);
+  /* single pass: sizes, eps, pointers, workspace; its grid needs n2 % 4 == 0 */
+  CHECK(is_refusal(fa_sinkhorn_fused(dummy, 0, 4, 0.1, da, da, 10, 0, 1, di, da, NULL, NULL, NULL, 0, NULL)));
+  CHECK(is_refusal(fa_sinkhorn_fused(dummy, 4, 4, 0.0, da, da, 10, 0, 1, di, da, NULL, NULL, NULL, 0, NULL)));
+  CHECK(is_refusal(fa_sinkhorn_fused(NULL, 4, 4, 0.1, da, da, 10, 0, 1, di, da, NULL, NULL, NULL, 0, NULL)));
+  CHECK(fa_sinkhorn_fused(dummy, 4, 4, 0.1, da, da, 10, 0, 1, di, da, NULL, NULL, NULL, 0, NULL) == FA_ERR_WORKSPACE);
+  int32_t gr = -1, gc = -1;
+  CHECK(fa_sinkhorn_fused_grid(10, 6, &gr, &gc) == FA_ERR_SHAPE && gr == -1);
+  CHECK(fa_sinkhorn_fused_grid(10, 8, NULL, &gc) == FA_ERR_ARG);
+  const int32_t prev = fa_set_sync_spin_limit(0);   /* clamped to one poll */
+  CHECK(prev >= 1 && fa_set_sync_spin_limit(prev) == 1);
   /* End to end: parameter checks, then the workspace check */
   fa_params q = p;
   q.eps = 0;
@@ -185,6 +197,9 @@ static void arg_group(void) {
   CHECK(fa_align(&g1, &g2, NULL, NULL, 0, NULL, 0, &q, NULL, dummy, da, da, di, NULL, NULL, 0, NULL, NULL, &st, NULL, 0,
                  NULL) == FA_ERR_ARG);
   q = p; q.transpose_cost = 0; q.plan_in_ct = 1;
+  CHECK(fa_align(&g1, &g2, NULL, NULL, 0, NULL, 0, &q, NULL, dummy, da, da, di, NULL, NULL, 0, NULL, NULL, &st, NULL, 0,
+                 NULL) == FA_ERR_ARG);
+  q = p; q.sink_fused = 1; q.transpose_cost = 0; q.plan_in_ct = 1;
   CHECK(fa_align(&g1, &g2, NULL, NULL, 0, NULL, 0, &q, NULL, dummy, da, da, di, NULL, NULL, 0, NULL, NULL, &st, NULL, 0,
                  NULL) == FA_ERR_ARG);
   q = p; q.check_every = 0;

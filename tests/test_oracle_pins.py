@@ -543,3 +543,34 @@ def test_learned_start_fallback_rule(probe):
     good = _run(n, e1, n, e2, X1, X2, L, p2, b_init=ref["b"])
     assert good["fell_back"] == 0 and good["cold_iters"] == -1 and good["warm_err"] <= 1e-9
     assert good["iters"][0] == good["warm_iters"] <= 2
+
+
+def test_sinkhorn_iterates_obey_the_bounds_behind_the_single_pass():
+    """Eq. (3) iterates obey the two bounds that let the single-pass iteration form
+    2^y with y = (a_j + b_i - C_ij)/eps in FP32 without a running maximum: after an
+    a-update every plan entry is at most nu_j (the column sums are nu_j exactly);
+    after a b-update every row sums to mu_i, so the next a-update leaves each row
+    sum at least mu_i * min_j nu_j.  The row bound does not hold after the first
+    a-update from an arbitrary start, which is why the first two iterations run the
+    two-pass form.  Checked on the oracle's own iterates, for costs spread over
+    hundreds of eps and for n1 != n2."""
+    r = np.random.default_rng(12)
+    for n1, n2, eps, spread in [(40, 55, 0.05, 20.0), (70, 30, 0.02, 8.0), (25, 25, 0.1, 50.0)]:
+        C = r.random((n1, n2)) * spread + np.add.outer(r.random(n1), r.random(n2)) * spread
+        mu, nu = 1.0 / n1, 1.0 / n2
+        a = r.standard_normal(n2) * 3.0
+        b = r.standard_normal(n1) * 3.0
+        b[0] = -200.0 * eps       # a start that starves row 0
+        for t in range(12):
+            a1, b1, _, _ = O.sinkhorn(C, eps, 1, a0=a, b0=b)
+            S_a = O.plan(C, a1, b, eps)     # after the a-update of iteration t
+            assert np.allclose(S_a.sum(0), nu, rtol=1e-10, atol=0)
+            assert (S_a <= nu * (1 + 1e-10)).all()
+            rows = S_a.sum(1)
+            if t >= 1:
+                assert (rows >= mu * nu * (1 - 1e-10)).all(), (t, rows.min(), mu * nu)
+            elif n1 == 40:
+                assert rows[0] < 1e-30 * mu * nu    # the starved row: no bound after the first a-update
+            S_b = O.plan(C, a1, b1, eps)    # after the b-update
+            assert np.allclose(S_b.sum(1), mu, rtol=1e-10, atol=0)
+            a, b = a1, b1
