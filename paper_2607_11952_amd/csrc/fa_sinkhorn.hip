@@ -538,6 +538,30 @@ __device__ __forceinline__ double fuse_value(uint64_t x) {
   return __longlong_as_double(static_cast<long long>(x & ~0xffull));
 }
 
+// v + (v of the lane the DPP control selects), on both halves of an FP64 value; lanes
+// outside row_mask add 0.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ double dpp_add(double v) {
+  const int lo = __double2loint(v), hi = __double2hiint(v);
+  const int lo2 = __builtin_amdgcn_update_dpp(0, lo, CTRL, ROW_MASK, 0xf, false);
+  const int hi2 = __builtin_amdgcn_update_dpp(0, hi, CTRL, ROW_MASK, 0xf, false);
+  return v + __hiloint2double(hi2, lo2);
+}
+
+// Sum over aligned groups of g lanes (g a power of two <= 64), in a fixed order,
+// without leaving the vector unit: quad swaps, half-row and row mirrors, then row
+// broadcasts.  The group's sum ends in its last lane (every lane of the group for
+// g <= 16).
+__device__ __forceinline__ double group_sum(double v, int g) {
+  if (g >= 2) v = dpp_add<0xB1, 0xf>(v);   // quad_perm [1,0,3,2]
+  if (g >= 4) v = dpp_add<0x4E, 0xf>(v);   // quad_perm [2,3,0,1]
+  if (g >= 8) v = dpp_add<0x141, 0xf>(v);  // row_half_mirror
+  if (g >= 16) v = dpp_add<0x140, 0xf>(v); // row_mirror
+  if (g >= 32) v = dpp_add<0x142, 0xa>(v); // row_bcast:15 into rows 1 and 3
+  if (g >= 64) v = dpp_add<0x143, 0xc>(v); // row_bcast:31 into rows 2 and 3
+  return v;
+}
+
 // The rows of one row group, for one partner workgroup (one column slice), as a
 // pipeline over batches of K rows: load, then produce (2^y of the batch's entries,
 // its partial row sums published by wave 0), then consume (every wave forms the
@@ -680,10 +704,13 @@ struct FusePipe {
     const int64_t ib = row0 + static_cast<int64_t>(t) * K;
     double rs[K];
     if (K * gc <= 64 && __all((x0 & 0xffull) == tag)) {
-      double v = lane < K * gc ? fuse_value(x0) : 0.0;
-      for (int o = 1; o < gc; o <<= 1) v += __shfl_xor(v, o, 64);  // gc is a power of two
+      const double v = group_sum(lane < K * gc ? fuse_value(x0) : 0.0, gc);  // gc is a power of two
 #pragma unroll
-      for (int k = 0; k < K; ++k) rs[k] = __shfl(v, k * gc < 64 ? k * gc : 0, 64);
+      for (int k = 0; k < K; ++k) {
+        const int last = (k + 1) * gc - 1 < 64 ? (k + 1) * gc - 1 : 63;
+        rs[k] = __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), last),
+                                 __builtin_amdgcn_readlane(__double2loint(v), last));
+      }
     } else {
       gather(ib, rs);
     }
