@@ -240,7 +240,7 @@ def ingest_counters(fetch_dir, write_dir, workload="cl120k:120000x120000"):
         wb, _ = per_kernel(write, wf, prefix)
         if fb is None or wb is None:
             continue
-        alg = algorithmic_bytes(kind, n, n, 0, 0, chunk, 2, 6)
+        alg = algorithmic_bytes(kind, n, n, 0, 0, chunk, 2, 6, transposed=False)  # the headline keeps no C^T
         rec["kernels"][kind] = dict(workload=workload, kernel=prefix, launches=nl, bytes_per_launch=fb + wb,
                                     fetch_bytes=fb, write_bytes=wb, algorithmic_bytes=alg,
                                     source_digest=source_digest(kind))
