@@ -82,13 +82,12 @@ constexpr int kFuseK = 2;
 constexpr int kFuseMaxGrid = 2048;
 constexpr int32_t kFuseSpinDefault = 1 << 22;
 
-// Partners per row: the smallest power of two whose slices fit kFuseQ quads per thread.
+// Partners per row: the fewest whose slices fit kFuseQ quads per thread (more
+// partners would only mean fewer row groups on the same co-resident grid).
 static int fuse_partners(int32_t n2) {
   const int64_t nq = n2 / 4;
   const int64_t need = (nq + 256 * kFuseQ - 1) / (256 * kFuseQ);
-  int gc = 1;
-  while (gc < need) gc <<= 1;
-  return gc;
+  return static_cast<int>(need > 0 ? need : 1);
 }
 static int fuse_groups_cap(int32_t n2) {
   const int gc = fuse_partners(n2);
@@ -577,7 +576,7 @@ struct FusePipe {
   const float *C;
   int32_t n2;
   double k2, eps, log_mu, mu;
-  int32_t gc, c, spin_limit;
+  int32_t gc, c, spin_limit, glog;  // 1 << glog lanes per row in the exchange (>= gc)
   uint32_t tag;
   int64_t row0, row1;
   double *b;
@@ -644,20 +643,21 @@ struct FusePipe {
                          __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
 
-  // This wave's snapshot of the batch's slots (lane l: row ib + l / gc, partner
-  // l mod gc; needs K * gc <= 64), loaded before the step's data loads so that
-  // reading it later does not wait for those (vector loads return in order).
-  // Lanes without a slot, and rows past the group, read as ready.  The read skips
+  // This wave's snapshot of the batch's slots (lane l: row ib + (l >> glog),
+  // partner l mod 2^glog; needs K << glog <= 64), loaded before the step's data
+  // loads so that reading it later does not wait for those (vector loads return
+  // in order).  Lanes without a slot, and rows past the group, read as ready.  The read skips
   // the CU's L1 and is served by the XCD's L2, where the stores of partners on the
   // same XCD land (the grid puts a row group's partners on one XCD); it may miss a
   // store from another XCD, but a stale slot carries an earlier pass's tag, so the
   // batch then goes to the device-coherent gather.
   __device__ __forceinline__ uint64_t snap(int64_t ib) const {
     const int lane = threadIdx.x & 63;
-    if (lane >= K * gc || ib + lane / gc >= row1) return tag;
-    // rows ib .. ib+K-1 are consecutive, so lane's slot is ib * gc + lane: a uniform
-    // base plus the lane, with no per-lane address kept across the loop
-    return __hip_atomic_load(part + ib * gc + lane, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    const int k = lane >> glog, q = lane & ((1 << glog) - 1);
+    if (k >= K || q >= gc || ib + k >= row1) return tag;
+    // a uniform base plus a small per-lane offset, with no per-lane address kept
+    // across the loop
+    return __hip_atomic_load(part + ib * gc + (k * gc + q), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
   }
 
   // Device-coherent gather (bounded wait): until every partner's slot of the
@@ -703,11 +703,12 @@ struct FusePipe {
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int64_t ib = row0 + static_cast<int64_t>(t) * K;
     double rs[K];
-    if (K * gc <= 64 && __all((x0 & 0xffull) == tag)) {
-      const double v = group_sum(lane < K * gc ? fuse_value(x0) : 0.0, gc);  // gc is a power of two
+    const int g = 1 << glog;
+    if ((K << glog) <= 64 && __all((x0 & 0xffull) == tag)) {
+      const double v = group_sum((lane >> glog) < K && (lane & (g - 1)) < gc ? fuse_value(x0) : 0.0, g);
 #pragma unroll
       for (int k = 0; k < K; ++k) {
-        const int last = (k + 1) * gc - 1 < 64 ? (k + 1) * gc - 1 : 63;
+        const int last = (k + 1) * g - 1 < 64 ? (k + 1) * g - 1 : 63;
         rs[k] = __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), last),
                                  __builtin_amdgcn_readlane(__double2loint(v), last));
       }
@@ -748,7 +749,7 @@ struct FusePipe {
   __device__ __forceinline__ void step(int t, int nb, f32x4 (&x)[K][Q], double (&bx)[K], f32x4 (&y)[K][Q],
                                        double (&by)[K], f32x4 (&w)[K][Q], double (&bw)[K], double (&red)[2][K][4]) {
     uint64_t x0 = 0;
-    if (K * gc <= 64) x0 = snap(row0 + static_cast<int64_t>(t) * K);
+    if ((K << glog) <= 64) x0 = snap(row0 + static_cast<int64_t>(t) * K);
     asm volatile("" ::: "memory");
     load(t + 3, w, bw);
     asm volatile("" ::: "memory");
@@ -768,7 +769,7 @@ __global__ __launch_bounds__(256, 2) void k_sink_fused(const float *__restrict__
                                                        const double *__restrict__ bufA0,
                                                        const double *__restrict__ bufA1, int32_t cur,
                                                        double *__restrict__ b, double k2, double eps, double log_mu,
-                                                       double mu, int32_t gc, int32_t gr, uint32_t tag,
+                                                       double mu, int32_t gc, int32_t glog, int32_t gr, uint32_t tag,
                                                        uint64_t *__restrict__ part, double *__restrict__ pcol,
                                                        SinkCtl *__restrict__ ctl, int32_t spin_limit) {
   if (ctl->done) return;
@@ -798,6 +799,7 @@ __global__ __launch_bounds__(256, 2) void k_sink_fused(const float *__restrict__
   F.c = c;
   F.tag = tag;
   F.spin_limit = spin_limit;
+  F.glog = glog;
   F.row0 = static_cast<int64_t>(r) * n1 / gr;
   F.row1 = static_cast<int64_t>(r + 1) * n1 / gr;
   F.b = b;
@@ -950,14 +952,15 @@ int run_sinkhorn(const float *C, const float *Ct, int32_t n1, int32_t n2, double
     const int is_check = it > 0 && (it % check_every == 0);
     if (fused && it >= 2) {
       const float *cC = C;
-      int32_t cn1 = n1, cn2 = n2, ccur = cur, gc = fg.gc, gr = fg.gr, sp = spin;
+      int32_t cn1 = n1, cn2 = n2, ccur = cur, gc = fg.gc, gr = fg.gr, sp = spin, glog = 0;
+      while ((1 << glog) < gc) ++glog;
       uint32_t tag = static_cast<uint32_t>((it - 2) % 255 + 1);  // consecutive passes never share a tag
       const double *ca0 = a, *ca1 = w.a_next;
       double *cb = b, *cpcol = w.pcol;
       uint64_t *cpart = w.part;
       double ck2 = k2, ceps = eps, clog_mu = log_mu, cmu = mu;
       SinkCtl *cctl = ctl;
-      void *args[] = {&cC, &cn1, &cn2, &ca0, &ca1, &ccur, &cb, &ck2, &ceps, &clog_mu, &cmu, &gc, &gr, &tag,
+      void *args[] = {&cC, &cn1, &cn2, &ca0, &ca1, &ccur, &cb, &ck2, &ceps, &clog_mu, &cmu, &gc, &glog, &gr, &tag,
                       &cpart, &cpcol, &cctl, &sp};
       FA_TIMED(tm, KK_FUSED, s,
                FA_HIP(hipLaunchCooperativeKernel(reinterpret_cast<const void *>(&k_sink_fused<kFuseQ, kFuseK>),
