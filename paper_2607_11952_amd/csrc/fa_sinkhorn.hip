@@ -659,6 +659,12 @@ struct FusePipe {
     // across the loop
     return __hip_atomic_load(part + ib * gc + (k * gc + q), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
   }
+  // With 33..64 partners a row takes the whole wave: one snapshot load per row.
+  __device__ __forceinline__ uint64_t snap_row(int64_t i) const {
+    const int lane = threadIdx.x & 63;
+    if (lane >= gc || i >= row1) return tag;
+    return __hip_atomic_load(part + i * gc + lane, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+  }
 
   // Device-coherent gather (bounded wait): until every partner's slot of the
   // batch's rows carries this pass's tag, then the row sums in partner order.
@@ -699,12 +705,19 @@ struct FusePipe {
   // Row sums of batch t from all partners (this wave's snapshot if every tag in it
   // is this pass's: a fixed butterfly within each row's gc lanes; else the gather),
   // b (partner 0, wave 0), and the batch's plan entries into cs.
-  __device__ __forceinline__ void consume(int t, const f32x4 (&x)[K][Q], uint64_t x0) {
+  __device__ __forceinline__ void consume(int t, const f32x4 (&x)[K][Q], uint64_t x0, uint64_t x1) {
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int64_t ib = row0 + static_cast<int64_t>(t) * K;
     double rs[K];
     const int g = 1 << glog;
-    if ((K << glog) <= 64 && __all((x0 & 0xffull) == tag)) {
+    if (K == 2 && glog == 6 && __all((x0 & 0xffull) == tag) && __all((x1 & 0xffull) == tag)) {
+      const double v0 = group_sum(lane < gc ? fuse_value(x0) : 0.0, 64);
+      const double v1 = group_sum(lane < gc ? fuse_value(x1) : 0.0, 64);
+      rs[0] = __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v0), 63),
+                               __builtin_amdgcn_readlane(__double2loint(v0), 63));
+      rs[K - 1] = __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v1), 63),
+                                   __builtin_amdgcn_readlane(__double2loint(v1), 63));
+    } else if ((K << glog) <= 64 && __all((x0 & 0xffull) == tag)) {
       const double v = group_sum((lane >> glog) < K && (lane & (g - 1)) < gc ? fuse_value(x0) : 0.0, g);
 #pragma unroll
       for (int k = 0; k < K; ++k) {
@@ -748,13 +761,19 @@ struct FusePipe {
   // while faster waves write the next step's.
   __device__ __forceinline__ void step(int t, int nb, f32x4 (&x)[K][Q], double (&bx)[K], f32x4 (&y)[K][Q],
                                        double (&by)[K], f32x4 (&w)[K][Q], double (&bw)[K], double (&red)[2][K][4]) {
-    uint64_t x0 = 0;
-    if ((K << glog) <= 64) x0 = snap(row0 + static_cast<int64_t>(t) * K);
+    uint64_t x0 = 0, x1 = 0;
+    const int64_t ib = row0 + static_cast<int64_t>(t) * K;
+    if ((K << glog) <= 64) {
+      x0 = snap(ib);
+    } else if (K == 2 && glog == 6) {
+      x0 = snap_row(ib);
+      x1 = snap_row(ib + 1);
+    }
     asm volatile("" ::: "memory");
     load(t + 3, w, bw);
     asm volatile("" ::: "memory");
     if (t + 2 < nb) produce(t + 2, y, by, red[t & 1]);
-    consume(t, x, x0);
+    consume(t, x, x0, x1);
   }
 };
 
@@ -919,6 +938,14 @@ static int fuse_grid(int32_t n1, int32_t n2, FuseGrid *g) {
   if (gr > cap) gr = cap;
   if (gr > rows) gr = rows;
   if (gr >= 8) gr -= gr % 8;
+  // A pass takes as long as a row group needs for its rows.  The partners of a row
+  // group share an XCD, so at most (slots / 8) / gc groups fit per XCD; where that
+  // layout fills under 5/8 of the co-resident slots (33..39 partners: one group
+  // per XCD), the two-pass form is faster and the single pass is not used.
+  const int64_t xcd_groups = 8 * ((slots / 8) / gc);
+  FA_REQUIRE(8 * xcd_groups * gc >= 5 * static_cast<int64_t>(slots), FA_ERR_SHAPE,
+             "single-pass Sinkhorn: %d partners per row fill %lld of %d co-resident slots", gc,
+             static_cast<long long>(xcd_groups * gc), slots);
   g->gc = gc;
   g->gr = static_cast<int>(gr);
   return FA_OK;

@@ -281,11 +281,12 @@ def _sinkhorn_case(n1, n2, seed, eps):
 
 @pytest.mark.parametrize("form", SINK_FORMS)
 @pytest.mark.parametrize("shape", [(600, 2500), (513, 301), (1, 7), (9, 1), (300, 2503), (2503, 300), (2050, 4100),
-                                   (300, 8200), (129, 20004), (3, 16388)])
+                                   (300, 8200), (129, 20004), (3, 16388), (40, 180004), (9, 262144)])
 def test_sinkhorn_fixed_iterations(api, shape, form):
     """All column passes (strips of C, rows of C^T, the single pass); odd sizes take
-    the scalar paths; n2 > 4096 splits each row of the single pass over 2, 4 or 8
-    partner workgroups, and n1 = 3 leaves most row groups of its grid empty."""
+    the scalar paths; n2 > 4096 splits each row of the single pass over 2 to 64
+    partner workgroups (3 and 5: not powers of two; 44 and 64: one exchange load per
+    row), and n1 = 3 leaves most row groups of its grid empty."""
     n1, n2 = shape
     eps = 0.05
     C = _sinkhorn_case(n1, n2, n1 + n2, eps)
@@ -337,6 +338,18 @@ def test_sinkhorn_tolerance_stop_matches_oracle(api, form):
     S = O.plan(C32, a.cpu().numpy(), b.cpu().numpy(), eps)
     assert np.abs(S.sum(0) - 1 / n2).sum() <= 2 * tol
     assert np.abs(S.sum(1) - 1 / n1).sum() <= 1e-7   # rows exact up to the FP32-exp resolution
+
+
+def test_sinkhorn_single_pass_grid_choice(api):
+    """The single pass runs where its co-resident grid is well filled (120k: 30
+    partners x 16 row groups; 262,144 columns: 64 x 8) and yields to the two-pass
+    form where a row group's partners would leave most slots idle (145k: 36
+    partners, one group per XCD)."""
+    assert api.sinkhorn_fused_grid(120000, 120000) == (16, 30)
+    assert api.sinkhorn_fused_grid(70000, 70000) == (24, 18)
+    assert api.sinkhorn_fused_grid(64, 262144) == (8, 64)
+    assert api.sinkhorn_fused_grid(145000, 145000) is None
+    assert api.sinkhorn_fused_grid(100, 4098) is None   # n2 not a multiple of 4
 
 
 @pytest.mark.parametrize("shape", [(700, 8200), (257, 4100), (2503, 2500)])
