@@ -629,8 +629,8 @@ struct FusePipe {
     }
 #pragma unroll
     for (int k = 0; k < K; ++k) {
-      const double v = wave_sum(sk[k]);
-      if (lane == 0) red[k][wv] = v;
+      const double v = group_sum(sk[k], 64);  // the wave's sum, in lane 63
+      if (lane == 63) red[k][wv] = v;
     }
     __syncthreads();
     const int64_t ib = row0 + static_cast<int64_t>(t) * K;
