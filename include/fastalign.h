@@ -304,9 +304,11 @@ int fa_sinkhorn_noalloc(const float *C, const float *Ct, int32_t n1, int32_t n2,
  * no row sum of the next plan falls below mu_i * min_j nu_j).  Results equal
  * fa_sinkhorn's up to summation order (same iteration count when both stop on
  * the same check).  Arguments as fa_sinkhorn minus Ct; ws >=
- * fa_sinkhorn_fused_workspace_size(n1, n2) bytes.  Needs n2 % 4 == 0 and a device
- * that co-schedules the grid (fa_sinkhorn_fused_grid); otherwise every iteration
- * takes the two-pass form.  The partners' waits are bounded (fa_set_sync_spin_limit):
+ * fa_sinkhorn_fused_workspace_size(n1, n2) bytes.  Needs n2 % 4 == 0, at most 64
+ * partners per row (n2 <= 262,144), a device that co-schedules the grid, and a
+ * grid that fills at least 5/8 of the co-resident workgroup slots (a row's partners
+ * share an XCD, so 33..39 partners leave most of them idle); otherwise every
+ * iteration takes the two-pass form (fa_sinkhorn_fused_grid says which).  The partners' waits are bounded (fa_set_sync_spin_limit):
  * a wait that gives up stops the solve, dev_iters becomes -1 and dev_err NaN, and
  * with host_iters/host_err the call returns FA_ERR_SYNC. */
 size_t fa_sinkhorn_fused_workspace_size(int32_t n1, int32_t n2);
@@ -314,7 +316,8 @@ int fa_sinkhorn_fused(const float *C, int32_t n1, int32_t n2, double eps, double
                       double tol, int32_t check_every, int32_t *dev_iters, double *dev_err, int32_t *host_iters,
                       double *host_err, void *ws, size_t ws_bytes, void *stream);
 /* The single-pass grid on the current device: *gr row groups x *gc partners per
- * row (host outputs).  FA_ERR_SHAPE if the single pass is not available there. */
+ * row (host outputs; gc is the fewest partners whose column slices of <= 4,096
+ * fit n2).  FA_ERR_SHAPE if the single pass is not used for this shape there. */
 int fa_sinkhorn_fused_grid(int32_t n1, int32_t n2, int32_t *gr, int32_t *gc);
 /* Bound on the polls of one partner wait of the single pass (>= 1; default
  * 4,194,304, about four seconds).  Process-wide; returns the previous bound. */
