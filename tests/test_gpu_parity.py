@@ -703,6 +703,31 @@ def test_align_nan_input_is_a_numeric_error(api):
     assert ex.value.status == binding.FA_ERR_NUMERIC
 
 
+def test_align_reports_an_abandoned_partner_wait(api):
+    """An inner solve whose single pass gives up a partner wait (the bound forced
+    to one poll from the host) makes fa_align return FA_ERR_SYNC instead of a plan;
+    with the bound restored the same alignment runs and matches the two-pass form."""
+    from paper_2607_11952_amd import binding
+    lib = binding.load()
+    pr = make_pair(CONFIGS["er1k"], n1=6000)
+    assert api.sinkhorn_fused_grid(pr.n1, pr.n2)[1] >= 2
+    inp = api.AlignInputs.from_pair(pr)
+    kw = dict(eps=0.05, outer_iters=2, inner_iters=20)
+    prev = lib.raw("fa_set_sync_spin_limit")(1)
+    try:
+        with pytest.raises(binding.FastAlignError) as ex:
+            api.align(inp, api.params(**kw))
+        assert ex.value.status == binding.FA_ERR_SYNC
+    finally:
+        lib.raw("fa_set_sync_spin_limit")(prev)
+    res = api.align(inp, api.params(**kw))
+    ref = api.align(inp, api.params(sink_fused=0, **kw))
+    assert list(res.stats.inner_iters)[:2] == list(ref.stats.inner_iters)[:2] == [20, 20]
+    # the bar of the end-to-end tests: the second cost carries the first plan's rounding
+    assert float((res.S - ref.S).abs().max()) <= 1e-4 * float(ref.S.max())
+    assert float((res.argmax != ref.argmax).float().mean()) <= 1e-3
+
+
 def test_align_reports_convergence(api):
     """The stop rule (R13) and the status: an unreachable tolerance runs every solve
     to its cap and returns FA_WARN_NOT_CONVERGED; a tolerance met at the first
