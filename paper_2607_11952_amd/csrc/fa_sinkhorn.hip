@@ -89,9 +89,13 @@ static int fuse_partners(int32_t n2) {
   const int64_t need = (nq + 256 * kFuseQ - 1) / (256 * kFuseQ);
   return static_cast<int>(need > 0 ? need : 1);
 }
-static int fuse_groups_cap(int32_t n2) {
+// Row groups a grid can have: kFuseMaxGrid / gc, and no more than batches of rows.
+static int fuse_groups_cap(int32_t n1, int32_t n2) {
   const int gc = fuse_partners(n2);
-  return gc >= kFuseMaxGrid ? 1 : kFuseMaxGrid / gc;
+  const int64_t by_grid = gc >= kFuseMaxGrid ? 1 : kFuseMaxGrid / gc;
+  const int64_t by_rows = (static_cast<int64_t>(n1) + kFuseK - 1) / kFuseK;
+  const int64_t cap = by_grid < by_rows ? by_grid : by_rows;
+  return static_cast<int>(cap > 0 ? cap : 1);
 }
 
 // Which scratch a solve carves: the strip partials pm/ps serve the column pass
@@ -112,7 +116,7 @@ static void take_sink(Z &z, int32_t n1, int32_t n2, SinkMode mode) {
   z.template take<double>(1);
   if (mode == SINK_FUSED) {
     z.template take<uint64_t>(static_cast<size_t>(n1) * fuse_partners(n2));
-    z.template take<double>(static_cast<size_t>(fuse_groups_cap(n2)) * n2);
+    z.template take<double>(static_cast<size_t>(fuse_groups_cap(n1, n2)) * n2);
   }
 }
 
@@ -138,7 +142,7 @@ static int carve_sink(Carver &cv, int32_t n1, int32_t n2, SinkWs &w, SinkMode mo
   w.pcol = nullptr;
   if (mode == SINK_FUSED) {
     w.part = cv.take<uint64_t>(static_cast<size_t>(n1) * fuse_partners(n2));
-    w.pcol = cv.take<double>(static_cast<size_t>(fuse_groups_cap(n2)) * n2);
+    w.pcol = cv.take<double>(static_cast<size_t>(fuse_groups_cap(n1, n2)) * n2);
   }
   w.nsplit = L.nsplit;
   w.nerrblk = L.nmerge;
@@ -933,10 +937,8 @@ static int fuse_grid(int32_t n1, int32_t n2, FuseGrid *g) {
   FA_REQUIRE(slots > 0 && gc <= slots && gc <= n2 / 4, FA_ERR_SHAPE,
              "single-pass Sinkhorn: %d partners per row do not fit %d co-resident workgroups", gc, slots);
   int64_t gr = slots / gc;
-  const int64_t cap = fuse_groups_cap(n2);
-  const int64_t rows = (static_cast<int64_t>(n1) + kFuseK - 1) / kFuseK;
+  const int64_t cap = fuse_groups_cap(n1, n2);  // also no more groups than batches of rows
   if (gr > cap) gr = cap;
-  if (gr > rows) gr = rows;
   if (gr >= 8) gr -= gr % 8;
   // A pass takes as long as a row group needs for its rows.  The partners of a row
   // group share an XCD, so at most (slots / 8) / gc groups fit per XCD; where that
@@ -951,7 +953,7 @@ static int fuse_grid(int32_t n1, int32_t n2, FuseGrid *g) {
   return FA_OK;
 }
 
-std::atomic<int32_t> g_fuse_spin{kFuseSpinDefault};
+static std::atomic<int32_t> g_fuse_spin{kFuseSpinDefault};
 
 int run_sinkhorn(const float *C, const float *Ct, int32_t n1, int32_t n2, double eps, double *a, double *b,
                  int32_t max_iter, double tol, int32_t check_every, int32_t *dev_iters, double *dev_err, SinkWs &w,
