@@ -179,7 +179,7 @@ KERNEL_NAMES = {"sink_fused": "fa::k_sink_fused<4, 2>", "lse_col_t": "fa::k_lse_
                 "lse_col_partial": "fa::k_lse_col_partial<4, 4>", "lse_row": "fa::k_lse_row<4, 8>",
                 "cost_stage1": "fa::k_stage1<unsigned short, true, 2, 8, true>",
                 "cost_stage2": "fa::k_stage2<true, true>", "plan": "fa::k_plan<4, unsigned short>",
-                "featsim": "fa::k_featsim<unsigned short, unsigned short>"}
+                "featsim": "fa::k_featsim_dma"}
 
 
 def _counter_rows(d):

@@ -146,11 +146,14 @@ def test_feature_sim_fp32(api, shape):
 
 
 @pytest.mark.parametrize("shape", [(300, 260, 64, 45), (257, 300, 136, 72), (130, 129, 7, 200),
-                                   (600, 520, 128, 120), (513, 129, 0, 40), (256, 128, 24, 0)])
+                                   (600, 520, 128, 120), (513, 129, 0, 40), (256, 128, 24, 0),
+                                   (700, 530, 128, 2400), (1, 1, 8, 8)])
 def test_feature_sim_bf16(api, shape):
-    """128 x 128 tiles with ragged edges in both dimensions, several tiles each way;
-    K across several 64-element steps, vector (K*2 a multiple of 16) and element
-    staging; either product absent."""
+    """Both BF16 kernels: the direct-to-LDS one (K a multiple of 8: 256 x 128 tiles)
+    and the register-staged one (K = 45 or 7: 128 x 128 tiles, vector and element
+    staging).  Ragged edges in both dimensions, several tiles each way; K across
+    several 64-element steps with a partial last step (72, 120, 2,400); either
+    product absent; a single entry."""
     n1, n2, d, nL = shape
     r = np.random.default_rng(5)
     X1, X2 = r.standard_normal((n1, d)), r.standard_normal((n2, d))
