@@ -269,6 +269,11 @@ __device__ __forceinline__ void dma_mma(const uint8_t *la, const uint8_t *lb, in
   __builtin_amdgcn_sched_group_barrier(0x008, 16, 0);  // then 16 MFMAs
 }
 
+// e^-x as 2^(-x log2 e) with the hardware exp2 (about one ulp of its own): rounding
+// the FP32 argument adds at most |x| 2^-24 relative error, i.e. at most
+// |x| 2^-24 e^-x <= 2^-24 / e absolute for x >= 0.
+__device__ __forceinline__ float exp_neg(float x) { return __builtin_amdgcn_exp2f(-x * 1.44269504088896341f); }
+
 __global__ __launch_bounds__(512, 1) void k_featsim_dma(const uint16_t *__restrict__ X1, const uint16_t *__restrict__ X2,
                                                         int32_t d, const uint16_t *__restrict__ R1,
                                                         const uint16_t *__restrict__ R2, int32_t nL, int32_t n1,
@@ -348,7 +353,7 @@ __global__ __launch_bounds__(512, 1) void k_featsim_dma(const uint16_t *__restri
       for (int r = 0; r < 16; ++r) {
         const int row = m0 + wm * 64 + p * 32 + (r >> 2) * 8 + (lane >> 5) * 4 + (r & 3);
         if (row < n1 && col < n2)
-          C[static_cast<int64_t>(row) * n2 + col] = alpha * expf(-accR[p][q][r]) + beta * expf(-accX[p][q][r]);
+          C[static_cast<int64_t>(row) * n2 + col] = alpha * exp_neg(accR[p][q][r]) + beta * exp_neg(accX[p][q][r]);
       }
     }
 }
