@@ -209,10 +209,15 @@ constexpr int kDmaBM = 256, kDmaBN = 128;
 constexpr int kDmaStep = 64;                       // K elements per stage: 128 bytes per row
 constexpr int kDmaLoads = (kDmaBM + kDmaBN) / 64;  // load instructions per wave per stage (1 KB each)
 
-// Buffer resource over a row-major [rows x K] BF16 operand (rows * K * 2 < 2^31
-// bytes): a load at or past its end returns zero.
-__device__ __forceinline__ __amdgpu_buffer_rsrc_t dma_rsrc(const uint16_t *M, int32_t rows, int32_t K) {
-  return __builtin_amdgcn_make_buffer_rsrc(const_cast<uint16_t *>(M), 0, rows * K * 2, 0x00020000);
+// Buffer resource over the rows [row0, row0 + nr) of a row-major [rows x K] BF16
+// operand that one tile reads, nr = min(tile_rows, rows - row0) (row0 < rows): a
+// load at or past its end returns zero, and offsets stay below tile_rows * K * 2
+// bytes whatever the operand's size.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t dma_rsrc(const uint16_t *M, int32_t rows, int32_t K, int row0,
+                                                           int tile_rows) {
+  const int nr = rows - row0 < tile_rows ? rows - row0 : tile_rows;
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<uint16_t *>(M + static_cast<int64_t>(row0) * K), 0, nr * K * 2,
+                                           0x00020000);
 }
 
 // The 16-byte piece p of row r of a stage sits in slot p ^ dma_swz(r) of the row's
@@ -220,19 +225,20 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t dma_rsrc(const uint16_t *M, in
 // all banks whether the LDS serves 16 or 32 lanes per cycle.
 __device__ __forceinline__ int dma_swz(int r) { return (r ^ (r >> 3)) & 7; }
 
-// Rows [row0, row0 + ROWS) x K elements [k0, k0 + 64) of the operand into a stage
-// (ROWS x 128 bytes).  Each instruction writes 1 KB (eight rows) of LDS, lane l at
-// byte 16 l, so lane l fetches the piece its slot holds; pieces past K or past the
-// last row are given an offset past the end and arrive as zeros.
+// The tile's ROWS rows x K elements [k0, k0 + 64) of the operand (resource rs from
+// dma_rsrc, nr valid rows) into a stage (ROWS x 128 bytes).  Each instruction
+// writes 1 KB (eight rows) of LDS, lane l at byte 16 l, so lane l fetches the piece
+// its slot holds; pieces past K or past the last row are given an offset past the
+// end and arrive as zeros.
 template <int ROWS>
-__device__ __forceinline__ void dma_stage(__amdgpu_buffer_rsrc_t rs, int32_t rows, int32_t K, int row0, int k0,
-                                          uint8_t *lds, int wv, int lane) {
+__device__ __forceinline__ void dma_stage(__amdgpu_buffer_rsrc_t rs, int32_t nr, int32_t K, int k0, uint8_t *lds,
+                                          int wv, int lane) {
 #pragma unroll
   for (int i = 0; i < ROWS / 64; ++i) {
     const int g = i * 8 + wv;  // 1 KB block: rows 8g .. 8g+7
     const int r = 8 * g + (lane >> 3);
     const int k = k0 + 8 * ((lane & 7) ^ dma_swz(r));
-    const uint32_t off = row0 + r < rows && k < K ? (static_cast<uint32_t>(row0 + r) * K + k) * 2u : 0x80000000u;
+    const uint32_t off = r < nr && k < K ? (static_cast<uint32_t>(r) * K + k) * 2u : 0x80000000u;
     // the LDS operand is the wave's block base (M0); a generic-to-LDS address-space cast
     __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, (__attribute__((address_space(3))) void *)(lds + g * 1024), 16, off, 0,
                                              0, 0);
@@ -309,16 +315,18 @@ __global__ __launch_bounds__(512, 1) void k_featsim_dma(const uint16_t *__restri
   // the K steps of the encoding product, then those of the attribute product
   const int nR = (nL + kDmaStep - 1) / kDmaStep, nX = (d + kDmaStep - 1) / kDmaStep;
   const int nc = nR + nX;
-  const __amdgpu_buffer_rsrc_t rR1 = dma_rsrc(R1, n1, nL), rR2 = dma_rsrc(R2, n2, nL);
-  const __amdgpu_buffer_rsrc_t rX1 = dma_rsrc(X1, n1, d), rX2 = dma_rsrc(X2, n2, d);
+  // resources over this tile's rows of each operand (m0 < n1, n0 < n2)
+  const int nm = n1 - m0 < kDmaBM ? n1 - m0 : kDmaBM, nn = n2 - n0 < kDmaBN ? n2 - n0 : kDmaBN;
+  const __amdgpu_buffer_rsrc_t rR1 = dma_rsrc(R1, n1, nL, m0, kDmaBM), rR2 = dma_rsrc(R2, n2, nL, n0, kDmaBN);
+  const __amdgpu_buffer_rsrc_t rX1 = dma_rsrc(X1, n1, d, m0, kDmaBM), rX2 = dma_rsrc(X2, n2, d, n0, kDmaBN);
   auto issue = [&](int c) {
     uint8_t *la = ring[c % 3], *lb = la + kDmaBM * 128;
     if (c < nR) {
-      dma_stage<kDmaBM>(rR1, n1, nL, m0, c * kDmaStep, la, wv, lane);
-      dma_stage<kDmaBN>(rR2, n2, nL, n0, c * kDmaStep, lb, wv, lane);
+      dma_stage<kDmaBM>(rR1, nm, nL, c * kDmaStep, la, wv, lane);
+      dma_stage<kDmaBN>(rR2, nn, nL, c * kDmaStep, lb, wv, lane);
     } else {
-      dma_stage<kDmaBM>(rX1, n1, d, m0, (c - nR) * kDmaStep, la, wv, lane);
-      dma_stage<kDmaBN>(rX2, n2, d, n0, (c - nR) * kDmaStep, lb, wv, lane);
+      dma_stage<kDmaBM>(rX1, nm, d, (c - nR) * kDmaStep, la, wv, lane);
+      dma_stage<kDmaBN>(rX2, nn, d, (c - nR) * kDmaStep, lb, wv, lane);
     }
   };
   // Step c: wait for this wave's loads of step c (those of step c+1 may stay in
@@ -359,12 +367,10 @@ __global__ __launch_bounds__(512, 1) void k_featsim_dma(const uint16_t *__restri
 }
 
 // Operands the direct-to-LDS kernel takes: whole 16-byte pieces (K a multiple of
-// 8, 16-byte aligned rows) and each operand under 2^31 bytes (32-bit buffer offsets).
-static bool dma_operands(const void *A, const void *B, int32_t n1, int32_t n2, int32_t K) {
-  const int64_t lim = int64_t(1) << 31;
+// 8, 16-byte aligned rows) and a tile's rows under 2^31 bytes (32-bit buffer offsets).
+static bool dma_operands(const void *A, const void *B, int32_t K) {
   return K == 0 || (K % 8 == 0 && (reinterpret_cast<uintptr_t>(A) & 15) == 0 &&
-                    (reinterpret_cast<uintptr_t>(B) & 15) == 0 && int64_t(n1) * K * 2 < lim &&
-                    int64_t(n2) * K * 2 < lim);
+                    (reinterpret_cast<uintptr_t>(B) & 15) == 0 && int64_t(kDmaBM) * K * 2 < (int64_t(1) << 31));
 }
 
 int launch_feature_sim(const void *X1, const void *X2, int32_t n1, int32_t n2, int32_t d, int32_t xdt,
@@ -373,7 +379,7 @@ int launch_feature_sim(const void *X1, const void *X2, int32_t n1, int32_t n2, i
   if (n1 == 0 || n2 == 0) return FA_OK;
   const int nb = ceil_div(n1, kTile) * ceil_div(n2, kTile);
   const float al = static_cast<float>(alpha);
-  if (xdt == FA_BF16 && rdt == FA_BF16 && dma_operands(X1, X2, n1, n2, d) && dma_operands(R1, R2, n1, n2, nL))
+  if (xdt == FA_BF16 && rdt == FA_BF16 && dma_operands(X1, X2, d) && dma_operands(R1, R2, nL))
     FA_LAUNCH(k_featsim_dma, dim3(ceil_div(n1, kDmaBM) * ceil_div(n2, kDmaBN)), dim3(512), 0, s,
               static_cast<const uint16_t *>(X1), static_cast<const uint16_t *>(X2), d,
               static_cast<const uint16_t *>(R1), static_cast<const uint16_t *>(R2), nL, n1, n2, al, C);

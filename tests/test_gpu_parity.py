@@ -172,6 +172,34 @@ def test_feature_sim_bf16(api, shape):
     assert np.abs(got - exact).max() < 0.02
 
 
+@pytest.mark.parametrize("big", ["rows1", "rows2"])
+def test_feature_sim_bf16_operand_past_2gib(api, big):
+    """An encoding operand of 140,000 x 8,000 BF16 (2.24 GB, past what one 32-bit
+    buffer range covers) on either side: the direct-to-LDS kernel addresses each
+    tile's rows from the tile's own base.  Sampled entries, among them the last
+    rows and those whose byte offset from the operand's start crosses 2^31, against
+    the oracle's single-entry form on the same rounded rows."""
+    n_big, n_small, d, nL = 140000, 1000, 8, 8000
+    n1, n2 = (n_big, n_small) if big == "rows1" else (n_small, n_big)
+    g = torch.Generator(device="cuda").manual_seed(17)
+    R1 = (torch.rand((n1, nL), device="cuda", generator=g) * (3.0 / nL)).to(torch.bfloat16)
+    R2 = (torch.rand((n2, nL), device="cuda", generator=g) * (3.0 / nL)).to(torch.bfloat16)
+    X1 = torch.nn.functional.normalize(torch.randn((n1, d), device="cuda", generator=g), dim=1).to(torch.bfloat16)
+    X2 = torch.nn.functional.normalize(torch.randn((n2, d), device="cuda", generator=g), dim=1).to(torch.bfloat16)
+    got = api.feature_sim(X1, X2, R1, R2, 0.5)
+    torch.cuda.synchronize()
+    r = np.random.default_rng(5)
+    cross = (1 << 31) // (2 * nL)  # first row whose start lies past 2^31 bytes
+    i = np.concatenate([r.integers(0, n1, 2000), [n1 - 1, min(cross - 1, n1 - 1), min(cross, n1 - 1)]])
+    j = np.concatenate([r.integers(0, n2, 2000), [n2 - 1, min(cross, n2 - 1), min(cross - 1, n2 - 1)]])
+    ii, jj = torch.as_tensor(i, device="cuda"), torch.as_tensor(j, device="cuda")
+    f64 = lambda t, idx: t[idx].double().cpu().numpy()
+    x1, x2, r1, r2 = f64(X1, ii), f64(X2, jj), f64(R1, ii), f64(R2, jj)
+    want = np.array([O.similarity_entry(x1[q], x2[q], r1[q], r2[q], 0.5) for q in range(len(i))])
+    g_ = got[ii, jj].double().cpu().numpy()
+    assert np.allclose(g_, want, rtol=1e-5, atol=1e-5), np.abs(g_ - want).max()
+
+
 def test_l2_normalize_bf16_rounding_matches_torch(api):
     r = np.random.default_rng(6)
     X = torch.from_numpy(r.standard_normal((333, 77)).astype(np.float32)).cuda()
