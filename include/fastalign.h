@@ -209,7 +209,11 @@ int fa_l2_normalize(const float *X, int32_t n, int32_t d, void *out, int32_t out
  *   X1 [n1*d], X2 [n2*d]   (dtype x_dtype: FA_F32 or FA_BF16; d may be 0)
  *   R1 [n1*nL], R2 [n2*nL] (dtype r_dtype; nL may be 0)
  *   C_node float[n1*n2] (out).  FP32 operands use FP32 MFMA, BF16 operands
- *   BF16 MFMA; accumulation is FP32 in both. */
+ *   BF16 MFMA; accumulation is FP32 in both.  BF16 operands whose d and nL are
+ *   multiples of 8 and whose four pointers are 16-byte aligned take the faster
+ *   direct-to-LDS kernel (the exponentials there are the hardware exp2 of
+ *   -x log2(e), relative error at most |x| 2^-24 beyond the exp2's own ulp);
+ *   other shapes give the same products through a register-staged kernel. */
 int fa_feature_sim(const void *X1, const void *X2, int32_t n1, int32_t n2, int32_t d,
                    int32_t x_dtype, const void *R1, const void *R2, int32_t nL,
                    int32_t r_dtype, double alpha, float *C_node, void *stream);
