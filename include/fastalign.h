@@ -213,7 +213,7 @@ int fa_l2_normalize(const float *X, int32_t n, int32_t d, void *out, int32_t out
  *   multiples of 8 and whose four pointers are 16-byte aligned take the faster
  *   direct-to-LDS kernel (the exponentials there are the hardware exp2 of
  *   -x log2(e), relative error at most |x| 2^-24 beyond the exp2's own ulp);
- *   other shapes give the same products through a register-staged kernel. */
+ *   other shapes run a register-staged kernel with the library expf. */
 int fa_feature_sim(const void *X1, const void *X2, int32_t n1, int32_t n2, int32_t d,
                    int32_t x_dtype, const void *R1, const void *R2, int32_t nL,
                    int32_t r_dtype, double alpha, float *C_node, void *stream);
