@@ -189,9 +189,10 @@ def test_feature_sim_bf16_operand_past_2gib(api, big):
     got = api.feature_sim(X1, X2, R1, R2, 0.5)
     torch.cuda.synchronize()
     r = np.random.default_rng(5)
-    cross = (1 << 31) // (2 * nL)  # first row whose start lies past 2^31 bytes
-    i = np.concatenate([r.integers(0, n1, 2000), [n1 - 1, min(cross - 1, n1 - 1), min(cross, n1 - 1)]])
-    j = np.concatenate([r.integers(0, n2, 2000), [n2 - 1, min(cross, n2 - 1), min(cross - 1, n2 - 1)]])
+    cross = (1 << 31) // (2 * nL)  # the row whose bytes straddle offset 2^31; the next one starts past it
+    edge = [min(c, n_big - 1) for c in (cross - 1, cross, cross + 1)]
+    i = np.concatenate([r.integers(0, n1, 2000), [n1 - 1] + (edge if n1 == n_big else [0, 1, 2])])
+    j = np.concatenate([r.integers(0, n2, 2000), [n2 - 1] + (edge[::-1] if n2 == n_big else [2, 1, 0])])
     ii, jj = torch.as_tensor(i, device="cuda"), torch.as_tensor(j, device="cuda")
     f64 = lambda t, idx: t[idx].double().cpu().numpy()
     x1, x2, r1, r2 = f64(X1, ii), f64(X2, jj), f64(R1, ii), f64(R2, jj)
