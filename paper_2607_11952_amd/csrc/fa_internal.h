@@ -57,7 +57,7 @@ struct SinkWs {
   double *errp;   // per-block L1 error partials
   int32_t *ctl;   // [0] done flag, [1] iterations done, [2] which buffer holds a, [4] abandoned wait
   double *err;    // [1] final marginal error
-  uint64_t *part; // single-pass form (nullptr: two passes per iteration): tagged row partials [n1 * gc]
+  uint64_t *part; // single-pass form (nullptr: two passes per iteration): tagged row partials [n1 * fuse_stride(gc)]
   double *pcol;   //   column sums per row group [gr * n2]
   int nsplit, nerrblk;
 };

@@ -89,6 +89,12 @@ static int fuse_partners(int32_t n2) {
   const int64_t need = (nq + 256 * kFuseQ - 1) / (256 * kFuseQ);
   return static_cast<int>(need > 0 ? need : 1);
 }
+// Slots per row of the exchange: gc rounded up to a multiple of 8, so a batch of
+// kFuseK = 2 rows fills whole 128-byte lines.  A snapshot is served through the
+// CU's L1; with rows packed at gc slots a batch would share a line with the next
+// one, and the copy of that line brought in by one snapshot could serve the next
+// batch's snapshot before every partner had published it (a needless slow path).
+__host__ __device__ constexpr int fuse_stride(int gc) { return (gc + 7) & ~7; }
 // Row groups a grid can have: kFuseMaxGrid / gc, and no more than batches of rows.
 static int fuse_groups_cap(int32_t n1, int32_t n2) {
   const int gc = fuse_partners(n2);
@@ -115,7 +121,7 @@ static void take_sink(Z &z, int32_t n1, int32_t n2, SinkMode mode) {
   z.template take<SinkCtl>(1);
   z.template take<double>(1);
   if (mode == SINK_FUSED) {
-    z.template take<uint64_t>(static_cast<size_t>(n1) * fuse_partners(n2));
+    z.template take<uint64_t>(static_cast<size_t>(n1) * fuse_stride(fuse_partners(n2)));
     z.template take<double>(static_cast<size_t>(fuse_groups_cap(n1, n2)) * n2);
   }
 }
@@ -141,7 +147,7 @@ static int carve_sink(Carver &cv, int32_t n1, int32_t n2, SinkWs &w, SinkMode mo
   w.part = nullptr;
   w.pcol = nullptr;
   if (mode == SINK_FUSED) {
-    w.part = cv.take<uint64_t>(static_cast<size_t>(n1) * fuse_partners(n2));
+    w.part = cv.take<uint64_t>(static_cast<size_t>(n1) * fuse_stride(fuse_partners(n2)));
     w.pcol = cv.take<double>(static_cast<size_t>(fuse_groups_cap(n1, n2)) * n2);
   }
   w.nsplit = L.nsplit;
@@ -580,7 +586,7 @@ struct FusePipe {
   const float *C;
   int32_t n2;
   double k2, eps, log_mu, mu;
-  int32_t gc, c, spin_limit, glog;  // 1 << glog lanes per row in the exchange (>= gc)
+  int32_t gc, gs, c, spin_limit, glog;  // gs slots per row; 1 << glog lanes per row in the exchange (>= gc)
   uint32_t tag;
   int64_t row0, row1;
   double *b;
@@ -642,7 +648,7 @@ struct FusePipe {
 #pragma unroll
       for (int k = 0; k < K; ++k) bold[(t & 3) * K + k] = bx[k];  // read when batch t is consumed
     if (wv == 0 && lane < K && ib + lane < row1)
-      __hip_atomic_store(&part[(ib + lane) * gc + c],
+      __hip_atomic_store(&part[(ib + lane) * gs + c],
                          fuse_pack((red[lane][0] + red[lane][1]) + (red[lane][2] + red[lane][3]), tag),
                          __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
@@ -661,13 +667,13 @@ struct FusePipe {
     if (k >= K || q >= gc || ib + k >= row1) return tag;
     // a uniform base plus a small per-lane offset, with no per-lane address kept
     // across the loop
-    return __hip_atomic_load(part + ib * gc + (k * gc + q), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    return __hip_atomic_load(part + ib * gs + (k * gs + q), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
   }
   // With 33..64 partners a row takes the whole wave: one snapshot load per row.
   __device__ __forceinline__ uint64_t snap_row(int64_t i) const {
     const int lane = threadIdx.x & 63;
     if (lane >= gc || i >= row1) return tag;
-    return __hip_atomic_load(part + i * gc + lane, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    return __hip_atomic_load(part + i * gs + lane, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
   }
 
   // Device-coherent gather (bounded wait): until every partner's slot of the
@@ -682,7 +688,7 @@ struct FusePipe {
       for (int k = 0; k < K; ++k)
         if (ib + k < row1)
           for (int q = lane; q < gc; q += 64)
-            ready &= (__hip_atomic_load(&part[(ib + k) * gc + q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) &
+            ready &= (__hip_atomic_load(&part[(ib + k) * gs + q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) &
                       0xffull) == tag;
       if (__all(ready)) break;
       ++spins;
@@ -701,7 +707,7 @@ struct FusePipe {
       double v = 0.0;
       if (ib + k < row1)
         for (int q = lane; q < gc; q += 64)
-          v += fuse_value(__hip_atomic_load(&part[(ib + k) * gc + q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+          v += fuse_value(__hip_atomic_load(&part[(ib + k) * gs + q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
       rs[k] = wave_sum(v);
     }
   }
@@ -823,6 +829,7 @@ __global__ __launch_bounds__(256, 2) void k_sink_fused(const float *__restrict__
   F.tag = tag;
   F.spin_limit = spin_limit;
   F.glog = glog;
+  F.gs = fuse_stride(gc);
   F.row0 = static_cast<int64_t>(r) * n1 / gr;
   F.row1 = static_cast<int64_t>(r + 1) * n1 / gr;
   F.b = b;
@@ -972,7 +979,7 @@ int run_sinkhorn(const float *C, const float *Ct, int32_t n1, int32_t n2, double
   const bool fused = w.part != nullptr && max_iter >= 2 && fuse_grid(n1, n2, &fg) == FA_OK;
   // clear the exchange slots (tag 0 is never a pass's tag)
   if (fused)
-    FA_TRY(launch_fill_f64(reinterpret_cast<double *>(w.part), static_cast<int64_t>(n1) * fg.gc, 0.0, s));
+    FA_TRY(launch_fill_f64(reinterpret_cast<double *>(w.part), static_cast<int64_t>(n1) * fuse_stride(fg.gc), 0.0, s));
   const double mu = 1.0 / n1;
   const int32_t spin = g_fuse_spin.load();
   for (int it = 0; it <= max_iter; ++it) {
